@@ -1,0 +1,148 @@
+/*
+ * gc.h -- C ABI of libgc: exact triangle counting, per-edge triangle support,
+ * k-truss and truss decomposition on one AMD Instinct MI355X (gfx950).
+ *
+ * The operations follow the definitions of Samsi et al., "Static Graph
+ * Challenge: Subgraph Isomorphism" (2017):
+ *   - input graph: an edge list of integer vertex ids, weights 1, self-loops
+ *     removed, directed edges symmetrised (Sec. II);
+ *   - triangle count: the number of sets of three mutually adjacent vertices
+ *     (Sec. III-A; Alg. 3 computes it as a masked product);
+ *   - support of an edge: the number of triangles containing it, i.e. the
+ *     number of common neighbours of its endpoints (Sec. III-B, the row sums of
+ *     (EA == 2));
+ *   - k-truss: the largest subgraph in which every edge lies in at least k-2
+ *     triangles of that subgraph (Sec. III-B, Alg. 4);
+ *   - truss decomposition: the k-truss for every k >= 2 (Sec. III-B, last
+ *     paragraph).
+ * All arithmetic is integer and exact.
+ *
+ * Conventions shared by every call
+ *   Pointers prefixed d_ are device pointers (hipMalloc'd or torch tensors on
+ *   the current device); h_ are host pointers.  The caller owns every buffer
+ *   it passes; the library owns gc_graph handles and the device memory inside
+ *   them until gc_graph_free.
+ *
+ *   Canonical edge order: after normalisation the graph is the set of pairs
+ *   (u, v) with u < v, sorted lexicographically; the position of a pair is its
+ *   edge id (the row index of the incidence matrix E of Sec. III-B).  Every
+ *   per-edge output (support, k-truss mask, truss number) is written in that
+ *   order, so results are bit-comparable with a memcmp.
+ *
+ *   Streams: every call is ordered on `stream` (a hipStream_t; NULL is the
+ *   null stream).  Calls that return a host scalar synchronise the stream
+ *   before returning.  Device inputs must stay valid until the stream has
+ *   passed the call.
+ *
+ *   Errors: calls never abort.  They return GC_OK (0) or a negative status;
+ *   gc_last_error() gives a thread-local description of the last failure.  On
+ *   failure, outputs are unspecified and the handle stays valid.
+ *
+ *   Threading: one call at a time per handle (calls share the handle's device
+ *   workspace); different handles are independent.
+ *
+ *   Limits: n_vertices <= 2^31 - 1; the number of input pairs and the number of
+ *   edges must be < 2^31 (GC_EOVERFLOW otherwise).  Counts are int64.
+ */
+#ifndef GC_H_
+#define GC_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gc_graph gc_graph;
+typedef int32_t gc_status;
+typedef void *gc_stream; /* a hipStream_t */
+
+#define GC_OK 0
+#define GC_EINVAL (-1)     /* null pointer, negative size, bad flag, k < 2 */
+#define GC_ERANGE (-2)     /* a vertex id outside [0, n_vertices) */
+#define GC_ECAPACITY (-3)  /* output buffer shorter than required */
+#define GC_ENOMEM (-4)     /* device allocation failed */
+#define GC_EDEVICE (-5)    /* a HIP runtime error */
+#define GC_EOVERFLOW (-6)  /* a size beyond the limits above */
+
+/* gc_build_csr flags */
+#define GC_INPUT_ONE_BASED 0x1u /* ids are 1..n as in the challenge's files
+                                   (Sec. II); 1 is subtracted on input */
+
+/* Build a graph handle from raw edge pairs (Sec. II).
+ * d_src[i], d_dst[i] (i < n_pairs, device, int32) are the endpoints of pair i.
+ * Pairs may come in any order and direction and may repeat; self-loops are
+ * dropped and {u, v} / {v, u} / repeats collapse to one undirected edge.
+ * On success *out receives a new handle (free with gc_graph_free); on failure
+ * *out is set to NULL.  An id outside [0, n_vertices) (after the optional
+ * 1-based shift) gives GC_ERANGE.  Synchronises `stream`. */
+gc_status gc_build_csr(const int32_t *d_src, const int32_t *d_dst,
+                       int64_t n_pairs, int32_t n_vertices, uint32_t flags,
+                       gc_stream stream, gc_graph **out);
+
+/* Sizes of a handle: vertices, undirected edges m (canonical edge count) and
+ * the device bytes the handle currently holds.  Any output pointer may be
+ * NULL. */
+gc_status gc_graph_info(const gc_graph *g, int64_t *n_vertices,
+                        int64_t *n_edges, int64_t *device_bytes);
+
+/* Copy the canonical edge list (u < v, lexicographic; Sec. II / III-B rows of
+ * E) into d_u[0..m), d_v[0..m) (device, int32).  cap < m gives GC_ECAPACITY. */
+gc_status gc_graph_edges(gc_graph *g, int32_t *d_u, int32_t *d_v, int64_t cap,
+                         gc_stream stream);
+
+/* Copy the degree-oriented CSR used by the kernels.  Vertex r of the CSR is
+ * the vertex of rank r in the strict order (degree, id); each edge is stored
+ * once, from its lower-ranked to its higher-ranked endpoint (the strict
+ * lower-triangular part L of Alg. 3 in that order).
+ *   d_rank[0..n)        rank of each original vertex id
+ *   d_row_ptr[0..n+1)   row offsets
+ *   d_col[0..m)         rank of the head of each oriented edge, rows sorted
+ *   d_eid[0..m)         canonical edge id of each oriented edge
+ * Any output may be NULL.  cap_n < n+1 or cap_m < m gives GC_ECAPACITY. */
+gc_status gc_graph_oriented(gc_graph *g, int32_t *d_rank, int32_t *d_row_ptr,
+                            int32_t *d_col, int32_t *d_eid, int64_t cap_n,
+                            int64_t cap_m, gc_stream stream);
+
+/* Triangle count (Sec. III-A; Alg. 3's sum(A .* (L U)) / 2): the number of
+ * vertex triples that are pairwise adjacent, written to *h_count (host).
+ * Synchronises `stream`. */
+gc_status gc_triangle_count(gc_graph *g, gc_stream stream, int64_t *h_count);
+
+/* Per-edge support (Sec. III-B: row sums of (EA == 2); Alg. 2's C(u, v)):
+ * d_support[e] = number of triangles containing canonical edge e, for
+ * e < m (device, int32).  cap < m gives GC_ECAPACITY. */
+gc_status gc_edge_support(gc_graph *g, int32_t *d_support, int64_t cap,
+                          gc_stream stream);
+
+/* k-truss (Sec. III-B, Alg. 4): d_in_truss[e] = 1 if canonical edge e belongs
+ * to the maximal k-truss, else 0 (device, uint8, m entries).  Edges are
+ * removed in rounds: support is recomputed on the remaining edges, every edge
+ * with support < k-2 is dropped, and the edge list is compacted, until no
+ * edge is dropped.  *h_m_k (host, may be NULL) receives the number of edges in
+ * the k-truss.  k < 2 gives GC_EINVAL; k = 2 keeps every edge.
+ * Synchronises `stream`. */
+gc_status gc_ktruss(gc_graph *g, int32_t k, uint8_t *d_in_truss, int64_t cap,
+                    gc_stream stream, int64_t *h_m_k);
+
+/* Truss decomposition (Sec. III-B, last paragraph): d_truss[e] = the largest
+ * k such that canonical edge e belongs to the k-truss (>= 2), and *h_kmax the
+ * largest k with a non-empty k-truss (0 for an empty graph, 2 if there are
+ * edges but no triangle).  Either output may be NULL.  Synchronises `stream`. */
+gc_status gc_truss_decomposition(gc_graph *g, int32_t *d_truss, int64_t cap,
+                                 gc_stream stream, int32_t *h_kmax);
+
+/* Release a handle and its device memory (NULL is a no-op). */
+void gc_graph_free(gc_graph *g);
+
+/* Text for a status code (static storage). */
+const char *gc_status_str(gc_status status);
+
+/* Thread-local description of the last failure on this thread ("" if none). */
+const char *gc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GC_H_ */

@@ -13,7 +13,8 @@ independent cross-checks on tiny graphs.
 Function map (paper passage -> function)
   normalisation, Sec. II                      -> normalise
   triangle count, Sec. III-A                  -> triangle_count
-  per-edge support, Sec. III-B (EA, R == 2)   -> support
+  per-edge support, Sec. III-B (EA, R == 2)   -> support(method="definition")
+  per-edge support by triangle listing        -> support(method="listing")
   k-truss, Sec. III-B / Alg. 4 (bulk rounds)  -> ktruss(method="bulk")
   k-truss, one-at-a-time peeling              -> ktruss(method="peel")
   truss decomposition, Sec. III-B last para.  -> truss_decomposition
@@ -55,6 +56,8 @@ def _load():
         lib.oracle_triangle_count.restype = i64
         lib.oracle_support.argtypes = [i32, i64, P, P, P]
         lib.oracle_support.restype = ctypes.c_int
+        lib.oracle_support_listing.argtypes = [i32, i64, P, P, P]
+        lib.oracle_support_listing.restype = ctypes.c_int
         lib.oracle_ktruss_bulk.argtypes = [i32, i64, P, P, i32, P]
         lib.oracle_ktruss_bulk.restype = i32
         lib.oracle_ktruss_peel.argtypes = [i32, i64, P, P, i32, P]
@@ -110,12 +113,16 @@ def triangle_count(n: int, u, v) -> int:
     return int(t)
 
 
-def support(n: int, u, v) -> np.ndarray:
+def support(n: int, u, v, method: str = "definition") -> np.ndarray:
+    """Per-edge support.  ``definition``: |N(u) cap N(v)| edge by edge;
+    ``listing``: every triangle listed once and scattered to its 3 edges."""
     u, v = _i32(u), _i32(v)
     _check_canonical(u, v, n)
     s = np.zeros(max(len(u), 1), np.int32)
-    if _load().oracle_support(int(n), len(u), _p(u), _p(v), _p(s)) != 0:
-        raise MemoryError("oracle_support failed")
+    fn = {"definition": _load().oracle_support,
+          "listing": _load().oracle_support_listing}[method]
+    if fn(int(n), len(u), _p(u), _p(v), _p(s)) != 0:
+        raise MemoryError("oracle support failed")
     return s[:len(u)].copy()
 
 

@@ -242,32 +242,126 @@ int32_t oracle_ktruss_bulk(int32_t n, int64_t m, const int32_t *u,
 }
 
 /* ------------------------------------------------------------------------- */
+/* Support by triangle listing (an independent second route to the same       */
+/* numbers): list every triangle once by forward listing in the order of      */
+/* oracle_triangle_count, and add one to each of its three edges.  The         */
+/* listing also yields, per edge, the ids of the other two edges of each of    */
+/* its triangles (the "triangle index" used by peeling below).                 */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+  int64_t m;
+  int64_t *off;   /* m + 1: triangles of edge e are pair[off[e] .. off[e+1]) */
+  int32_t *pair;  /* 2 * 3T: the other two edge ids of each triangle of e   */
+} tri_index_t;
+
+static void tri_index_free(tri_index_t *t) {
+  free(t->off); free(t->pair);
+  t->off = NULL; t->pair = NULL;
+}
+
+/* Forward listing over oriented lists that carry edge ids.  If cnt != NULL,
+ * add 1 to cnt[e] for each edge of each triangle; if t != NULL, append the
+ * other two edge ids at fill[e].  Returns T. */
+static int64_t list_triangles(const adj_t *g, int64_t *cnt, tri_index_t *t, int64_t *fill) {
+  const int32_t n = g->n;
+  int64_t *deg = (int64_t *)malloc(sizeof(int64_t) * ((size_t)n + 1));
+  int64_t *ooff = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+  int32_t *out = (int32_t *)malloc(sizeof(int32_t) * (size_t)(g->m + 1));
+  int32_t *oid = (int32_t *)malloc(sizeof(int32_t) * (size_t)(g->m + 1));
+  if (!deg || !ooff || !out || !oid) { free(deg); free(ooff); free(out); free(oid); return -2; }
+  for (int32_t x = 0; x < n; ++x) deg[x] = g->off[x + 1] - g->off[x];
+  for (int32_t x = 0; x < n; ++x) {
+    ooff[x + 1] = ooff[x];
+    for (int64_t i = g->off[x]; i < g->off[x + 1]; ++i)
+      if (precedes(deg, x, g->nbr[i])) {
+        out[ooff[x + 1]] = g->nbr[i];
+        oid[ooff[x + 1]++] = g->eid[i];
+      }
+  }
+  int64_t T = 0;
+  for (int32_t x = 0; x < n; ++x) {
+    for (int64_t i = ooff[x]; i < ooff[x + 1]; ++i) {
+      const int32_t y = out[i];
+      const int32_t exy = oid[i];
+      int64_t a = ooff[x], ae = ooff[x + 1], b = ooff[y], be = ooff[y + 1];
+      while (a < ae && b < be) {
+        if (out[a] < out[b]) ++a;
+        else if (out[a] > out[b]) ++b;
+        else {                          /* triangle {x, y, z}, z = out[a] */
+          const int32_t exz = oid[a], eyz = oid[b];
+          ++T;
+          if (cnt) { cnt[exy]++; cnt[exz]++; cnt[eyz]++; }
+          if (t) {
+            int64_t q;
+            q = fill[exy]++; t->pair[2 * q] = exz; t->pair[2 * q + 1] = eyz;
+            q = fill[exz]++; t->pair[2 * q] = exy; t->pair[2 * q + 1] = eyz;
+            q = fill[eyz]++; t->pair[2 * q] = exy; t->pair[2 * q + 1] = exz;
+          }
+          ++a; ++b;
+        }
+      }
+    }
+  }
+  free(deg); free(ooff); free(out); free(oid);
+  return T;
+}
+
+int oracle_support_listing(int32_t n, int64_t m, const int32_t *u, const int32_t *v,
+                           int32_t *s) {
+  adj_t g;
+  if (adj_build(&g, n, m, u, v) != 0) return -2;
+  int64_t *cnt = (int64_t *)calloc((size_t)m + 1, sizeof(int64_t));
+  if (!cnt) { adj_free(&g); return -2; }
+  int64_t T = list_triangles(&g, cnt, NULL, NULL);
+  for (int64_t e = 0; e < m; ++e) s[e] = (int32_t)cnt[e];
+  free(cnt); adj_free(&g);
+  return T < 0 ? -2 : 0;
+}
+
+static int tri_index_build(const adj_t *g, tri_index_t *t) {
+  const int64_t m = g->m;
+  t->m = m;
+  t->off = (int64_t *)calloc((size_t)m + 1, sizeof(int64_t));
+  int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * ((size_t)m + 1));
+  if (!t->off || !fill) { free(fill); free(t->off); t->off = NULL; return -2; }
+  if (list_triangles(g, t->off + 1, NULL, NULL) < 0) { free(fill); return -2; }
+  for (int64_t e = 0; e < m; ++e) t->off[e + 1] += t->off[e];   /* prefix sums */
+  t->pair = (int32_t *)malloc(sizeof(int32_t) * (size_t)(2 * t->off[m] + 2));
+  if (!t->pair) { free(fill); return -2; }
+  memcpy(fill, t->off, sizeof(int64_t) * (size_t)m);
+  list_triangles(g, NULL, t, fill);
+  free(fill);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
 /* k-truss by one-edge-at-a-time peeling (an independent second algorithm, in  */
-/* the style of the truss work the paper cites in Sec. III-B): compute support */
-/* once, queue every edge below k-2, and on removing edge {a, b} decrement the */
-/* other two edges of every triangle {a, b, w} still fully present.            */
+/* the style of the truss work the paper cites in Sec. III-B): start from the  */
+/* support of every present edge, queue every edge below k-2, and on removing  */
+/* edge e decrement the other two edges of every triangle of e whose three     */
+/* edges are all still present (each destroyed triangle is counted once: it    */
+/* is destroyed by whichever of its edges is removed first).                   */
 /* in_out as for oracle_ktruss_bulk.  Returns 0 or < 0.                        */
 /* ------------------------------------------------------------------------- */
-static void peel_edge(const adj_t *g, const int32_t *u, const int32_t *v,
-                      int64_t e, uint8_t *alive, int32_t *s, int32_t thr,
-                      uint8_t *queued, int64_t *queue, int64_t *qtail) {
-  int32_t a = u[e], b = v[e];
+static void peel_edge(const tri_index_t *t, int64_t e, uint8_t *alive, int32_t *s,
+                      int32_t thr, uint8_t *queued, int64_t *queue, int64_t *qtail) {
   alive[e] = 0;
-  int64_t la = g->off[a], ha = g->off[a + 1], lb = g->off[b], hb = g->off[b + 1];
-  if (ha - la > hb - lb) {
-    int64_t t; int32_t tv = a; a = b; b = tv;
-    t = la; la = lb; lb = t; t = ha; ha = hb; hb = t;
-  }
-  for (int64_t i = la; i < ha; ++i) {
-    int64_t e1 = g->eid[i];
-    if (!alive[e1]) continue;
-    int64_t j = find_sorted(g->nbr, lb, hb, g->nbr[i]);
-    if (j < 0) continue;
-    int64_t e2 = g->eid[j];
-    if (!alive[e2]) continue;
-    /* triangle {a, b, w} is destroyed: both remaining edges lose one */
+  for (int64_t q = t->off[e]; q < t->off[e + 1]; ++q) {
+    const int32_t e1 = t->pair[2 * q], e2 = t->pair[2 * q + 1];
+    if (!alive[e1] || !alive[e2]) continue;     /* already destroyed */
     if (--s[e1] < thr && !queued[e1]) { queued[e1] = 1; queue[(*qtail)++] = e1; }
     if (--s[e2] < thr && !queued[e2]) { queued[e2] = 1; queue[(*qtail)++] = e2; }
+  }
+}
+
+/* support of every present edge within the present edges, from the index */
+static void present_support(const tri_index_t *t, const uint8_t *alive, int32_t *s) {
+  for (int64_t e = 0; e < t->m; ++e) {
+    int32_t c = 0;
+    if (alive[e])
+      for (int64_t q = t->off[e]; q < t->off[e + 1]; ++q)
+        c += alive[t->pair[2 * q]] && alive[t->pair[2 * q + 1]];
+    s[e] = c;
   }
 }
 
@@ -275,18 +369,20 @@ int32_t oracle_ktruss_peel(int32_t n, int64_t m, const int32_t *u,
                            const int32_t *v, int32_t k, uint8_t *in_out) {
   if (k < 2) return -1;
   adj_t g;
+  tri_index_t t = {0, NULL, NULL};
   if (adj_build(&g, n, m, u, v) != 0) return -2;
+  if (tri_index_build(&g, &t) != 0) { tri_index_free(&t); adj_free(&g); return -2; }
+  adj_free(&g);
   int32_t *s = (int32_t *)malloc(sizeof(int32_t) * (size_t)(m + 1));
   uint8_t *queued = (uint8_t *)calloc((size_t)m + 1, 1);
   int64_t *queue = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m + 1));
-  if (!s || !queued || !queue) { free(s); free(queued); free(queue); adj_free(&g); return -2; }
+  if (!s || !queued || !queue) { free(s); free(queued); free(queue); tri_index_free(&t); return -2; }
   int64_t qh = 0, qt = 0;
-  for (int64_t e = 0; e < m; ++e)
-    s[e] = in_out[e] ? common_neighbours(&g, u[e], v[e], in_out) : 0;
+  present_support(&t, in_out, s);
   for (int64_t e = 0; e < m; ++e)
     if (in_out[e] && s[e] < k - 2) { queued[e] = 1; queue[qt++] = e; }
-  while (qh < qt) peel_edge(&g, u, v, queue[qh++], in_out, s, k - 2, queued, queue, &qt);
-  free(s); free(queued); free(queue); adj_free(&g);
+  while (qh < qt) peel_edge(&t, queue[qh++], in_out, s, k - 2, queued, queue, &qt);
+  free(s); free(queued); free(queue); tri_index_free(&t);
   return 0;
 }
 
@@ -299,7 +395,7 @@ int32_t oracle_ktruss_peel(int32_t n, int64_t m, const int32_t *u,
 /* with edges but no triangle.                                                 */
 /*   method 0: bulk rounds (oracle_ktruss_bulk) per level, literally chained.  */
 /*   method 1: levelled peeling -- support kept across levels, edges peeled    */
-/*             one at a time with incremental decrements.                      */
+/*             one at a time with incremental decrements (triangle index).     */
 /* ------------------------------------------------------------------------- */
 int oracle_truss_decomposition(int32_t n, int64_t m, const int32_t *u,
                                const int32_t *v, int32_t method, int32_t *tau,
@@ -321,16 +417,19 @@ int oracle_truss_decomposition(int32_t n, int64_t m, const int32_t *u,
     }
   } else {
     adj_t g;
+    tri_index_t t = {0, NULL, NULL};
     if (adj_build(&g, n, m, u, v) != 0) { free(alive); return -2; }
+    if (tri_index_build(&g, &t) != 0) { tri_index_free(&t); adj_free(&g); free(alive); return -2; }
+    adj_free(&g);
     int32_t *s = (int32_t *)malloc(sizeof(int32_t) * (size_t)(m + 1));
     uint8_t *queued = (uint8_t *)calloc((size_t)m + 1, 1);
     int64_t *queue = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m + 1));
     int64_t *live = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m + 1));
     if (!s || !queued || !queue || !live) {
-      free(s); free(queued); free(queue); free(live); adj_free(&g); free(alive);
+      free(s); free(queued); free(queue); free(live); tri_index_free(&t); free(alive);
       return -2;
     }
-    for (int64_t e = 0; e < m; ++e) s[e] = common_neighbours(&g, u[e], v[e], NULL);
+    present_support(&t, alive, s);
     int64_t nlive = m;
     for (int64_t e = 0; e < m; ++e) live[e] = e;
     for (;; ++k) {
@@ -339,14 +438,14 @@ int oracle_truss_decomposition(int32_t n, int64_t m, const int32_t *u,
         int64_t e = live[i];
         if (s[e] < k - 2) { queued[e] = 1; queue[qt++] = e; }
       }
-      while (qh < qt) peel_edge(&g, u, v, queue[qh++], alive, s, k - 2, queued, queue, &qt);
+      while (qh < qt) peel_edge(&t, queue[qh++], alive, s, k - 2, queued, queue, &qt);
       int64_t w = 0;
       for (int64_t i = 0; i < nlive; ++i)
         if (alive[live[i]]) { tau[live[i]] = k; live[w++] = live[i]; }
       nlive = w;
       if (nlive == 0) break;
     }
-    free(s); free(queued); free(queue); free(live); adj_free(&g);
+    free(s); free(queued); free(queue); free(live); tri_index_free(&t);
   }
   *kmax = k - 1;
   free(alive);

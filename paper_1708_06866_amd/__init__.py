@@ -1,0 +1,246 @@
+"""Python binding of libgc (include/gc.h): exact triangle counting, per-edge
+support, k-truss and truss decomposition on an MI355X.
+
+This module only marshals arguments: torch tensors (device memory) become raw
+pointers, the current torch stream becomes the ``hipStream_t``, and status
+codes become exceptions.  Every step of the computation runs in libgc's HIP
+kernels; there is no CPU fallback -- if ``libgc.so`` is missing, or no GPU is
+visible, the calls raise.
+
+The functions carry the C names::
+
+    g = gc_build_csr(src, dst, n_vertices)          # raw pairs (int32, cuda)
+    gc_triangle_count(g)                            # -> int
+    gc_edge_support(g)                              # -> int32[m] (cuda)
+    gc_ktruss(g, k)                                 # -> (uint8[m] mask, m_k)
+    gc_truss_decomposition(g)                       # -> (int32[m] tau, kmax)
+
+``Graph`` wraps a handle with the same operations as methods.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgc.so")
+
+GC_OK = 0
+GC_EINVAL = -1
+GC_ERANGE = -2
+GC_ECAPACITY = -3
+GC_ENOMEM = -4
+GC_EDEVICE = -5
+GC_EOVERFLOW = -6
+GC_INPUT_ONE_BASED = 0x1
+
+_lib = None
+
+
+class GCError(RuntimeError):
+    def __init__(self, status: int, what: str, detail: str):
+        super().__init__("%s failed: %s (%s)" % (what, _status_str(status), detail))
+        self.status = status
+
+
+def lib():
+    """Load libgc.so (after torch, so both share torch's HIP runtime)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libgc.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+        L.gc_build_csr.argtypes = [P, P, i64, i32, u32, P, ctypes.POINTER(P)]
+        L.gc_graph_info.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
+        L.gc_graph_edges.argtypes = [P, P, P, i64, P]
+        L.gc_graph_oriented.argtypes = [P, P, P, P, P, i64, i64, P]
+        L.gc_triangle_count.argtypes = [P, P, ctypes.POINTER(i64)]
+        L.gc_edge_support.argtypes = [P, P, i64, P]
+        L.gc_ktruss.argtypes = [P, i32, P, i64, P, ctypes.POINTER(i64)]
+        L.gc_truss_decomposition.argtypes = [P, P, i64, P, ctypes.POINTER(i32)]
+        L.gc_graph_free.argtypes = [P]
+        L.gc_graph_free.restype = None
+        L.gc_status_str.argtypes = [i32]
+        L.gc_status_str.restype = ctypes.c_char_p
+        L.gc_last_error.argtypes = []
+        L.gc_last_error.restype = ctypes.c_char_p
+        for name in ("gc_build_csr", "gc_graph_info", "gc_graph_edges", "gc_graph_oriented",
+                     "gc_triangle_count", "gc_edge_support", "gc_ktruss",
+                     "gc_truss_decomposition"):
+            getattr(L, name).restype = i32
+        _lib = L
+    return _lib
+
+
+def _status_str(st: int) -> str:
+    try:
+        return lib().gc_status_str(st).decode()
+    except Exception:  # pragma: no cover
+        return str(st)
+
+
+def _check(st: int, what: str):
+    if st != GC_OK:
+        raise GCError(st, what, lib().gc_last_error().decode())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_i32(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError("%s must be a cuda tensor" % name)
+    if t.dtype != torch.int32:
+        raise TypeError("%s must be int32" % name)
+    return t.contiguous()
+
+
+def _ptr(t: torch.Tensor):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Graph:
+    """Owning wrapper of a gc_graph* handle."""
+
+    def __init__(self, handle: ctypes.c_void_p, device: torch.device):
+        self._h = handle
+        self.device = device
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("graph handle already freed")
+        return self._h
+
+    def free(self):
+        if self._h:
+            lib().gc_graph_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    # sizes ---------------------------------------------------------------
+    def info(self):
+        n, m, b = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().gc_graph_info(self.handle, ctypes.byref(n), ctypes.byref(m),
+                                   ctypes.byref(b)), "gc_graph_info")
+        return int(n.value), int(m.value), int(b.value)
+
+    @property
+    def n(self) -> int:
+        return self.info()[0]
+
+    @property
+    def m(self) -> int:
+        return self.info()[1]
+
+    # outputs -------------------------------------------------------------
+    def edges(self, stream=None):
+        return gc_graph_edges(self, stream)
+
+    def oriented(self, stream=None):
+        return gc_graph_oriented(self, stream)
+
+    def triangle_count(self, stream=None) -> int:
+        return gc_triangle_count(self, stream)
+
+    def edge_support(self, out=None, stream=None) -> torch.Tensor:
+        return gc_edge_support(self, out, stream)
+
+    def ktruss(self, k: int, out=None, stream=None):
+        return gc_ktruss(self, k, out, stream)
+
+    def truss_decomposition(self, out=None, stream=None):
+        return gc_truss_decomposition(self, out, stream)
+
+
+def _handle(g):
+    return g.handle if isinstance(g, Graph) else g
+
+
+def gc_build_csr(src: torch.Tensor, dst: torch.Tensor, n_vertices: int, flags: int = 0,
+                 stream=None) -> Graph:
+    src = _dev_i32(src, "src")
+    dst = _dev_i32(dst, "dst")
+    if src.numel() != dst.numel():
+        raise ValueError("src and dst differ in length")
+    h = ctypes.c_void_p()
+    st = lib().gc_build_csr(_ptr(src), _ptr(dst), src.numel(), int(n_vertices), int(flags),
+                            _stream(stream), ctypes.byref(h))
+    _check(st, "gc_build_csr")
+    return Graph(h, src.device)
+
+
+def gc_graph_info(g):
+    return g.info() if isinstance(g, Graph) else Graph(g, None).info()
+
+
+def gc_graph_edges(g: Graph, stream=None):
+    _, m, _ = g.info()
+    u = torch.empty(max(m, 1), dtype=torch.int32, device=g.device)
+    v = torch.empty(max(m, 1), dtype=torch.int32, device=g.device)
+    _check(lib().gc_graph_edges(g.handle, _ptr(u), _ptr(v), m, _stream(stream)), "gc_graph_edges")
+    return u[:m], v[:m]
+
+
+def gc_graph_oriented(g: Graph, stream=None):
+    n, m, _ = g.info()
+    rank = torch.empty(max(n, 1), dtype=torch.int32, device=g.device)
+    row_ptr = torch.empty(n + 1, dtype=torch.int32, device=g.device)
+    col = torch.empty(max(m, 1), dtype=torch.int32, device=g.device)
+    eid = torch.empty(max(m, 1), dtype=torch.int32, device=g.device)
+    _check(lib().gc_graph_oriented(g.handle, _ptr(rank), _ptr(row_ptr), _ptr(col), _ptr(eid),
+                                   n + 1, m, _stream(stream)), "gc_graph_oriented")
+    return rank[:n], row_ptr, col[:m], eid[:m]
+
+
+def gc_triangle_count(g: Graph, stream=None) -> int:
+    t = ctypes.c_int64()
+    _check(lib().gc_triangle_count(g.handle, _stream(stream), ctypes.byref(t)),
+           "gc_triangle_count")
+    return int(t.value)
+
+
+def gc_edge_support(g: Graph, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    _, m, _ = g.info()
+    if out is None:
+        out = torch.empty(max(m, 1), dtype=torch.int32, device=g.device)
+    _check(lib().gc_edge_support(g.handle, _ptr(out), out.numel(), _stream(stream)),
+           "gc_edge_support")
+    return out[:m]
+
+
+def gc_ktruss(g: Graph, k: int, out: torch.Tensor | None = None, stream=None):
+    _, m, _ = g.info()
+    if out is None:
+        out = torch.empty(max(m, 1), dtype=torch.uint8, device=g.device)
+    mk = ctypes.c_int64()
+    _check(lib().gc_ktruss(g.handle, int(k), _ptr(out), out.numel(), _stream(stream),
+                           ctypes.byref(mk)), "gc_ktruss")
+    return out[:m], int(mk.value)
+
+
+def gc_truss_decomposition(g: Graph, out: torch.Tensor | None = None, stream=None):
+    _, m, _ = g.info()
+    if out is None:
+        out = torch.empty(max(m, 1), dtype=torch.int32, device=g.device)
+    kmax = ctypes.c_int32()
+    _check(lib().gc_truss_decomposition(g.handle, _ptr(out), out.numel(), _stream(stream),
+                                        ctypes.byref(kmax)), "gc_truss_decomposition")
+    return out[:m], int(kmax.value)
+
+
+def build_graph(src, dst, n_vertices: int, device="cuda", one_based: bool = False) -> Graph:
+    """Convenience: host or device int32 pairs -> Graph on ``device``."""
+    s = torch.as_tensor(src, dtype=torch.int32).to(device)
+    d = torch.as_tensor(dst, dtype=torch.int32).to(device)
+    return gc_build_csr(s, d, n_vertices, GC_INPUT_ONE_BASED if one_based else 0)

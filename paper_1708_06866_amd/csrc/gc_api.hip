@@ -1,0 +1,198 @@
+// gc_api.hip -- handle accessors, status text, device memory helpers and the
+// counting entry points gc_triangle_count / gc_edge_support.
+#include <new>
+
+#include "gc_graph.h"
+
+namespace gc {
+
+static thread_local std::string t_last_error;
+
+void set_error(const std::string &msg) { t_last_error = msg; }
+void clear_error() { t_last_error.clear(); }
+
+gc_status dalloc(DeviceBuffer &b, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  if (b.ptr && b.bytes >= bytes) return GC_OK;
+  dfree(b);
+  hipError_t e = hipMalloc(&b.ptr, bytes);
+  if (e != hipSuccess) {
+    b.ptr = nullptr;
+    b.bytes = 0;
+    (void)hipGetLastError();
+    set_error(std::string("hipMalloc(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? GC_ENOMEM : GC_EDEVICE;
+  }
+  b.bytes = bytes;
+  return GC_OK;
+}
+
+void dfree(DeviceBuffer &b) {
+  if (b.ptr) (void)hipFree(b.ptr);
+  b.ptr = nullptr;
+  b.bytes = 0;
+}
+
+// Run `fn` with the handle's device current, restoring the caller's device.
+template <class F>
+static gc_status on_device(const gc_graph *g, F &&fn) {
+  int prev = 0;
+  GC_HIP(hipGetDevice(&prev));
+  if (prev != g->device) GC_HIP(hipSetDevice(g->device));
+  gc_status st = fn();
+  if (prev != g->device) (void)hipSetDevice(prev);
+  return st;
+}
+
+__global__ void k_slot_to_canonical(const int32_t *__restrict__ sup,
+                                    const int32_t *__restrict__ eid, int32_t m,
+                                    int32_t *__restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[eid[i]] = sup[i];
+}
+
+}  // namespace gc
+
+using namespace gc;
+
+extern "C" gc_status gc_graph_info(const gc_graph *g, int64_t *n_vertices, int64_t *n_edges,
+                                   int64_t *device_bytes) {
+  clear_error();
+  if (!g) {
+    set_error("gc_graph_info: NULL handle");
+    return GC_EINVAL;
+  }
+  if (n_vertices) *n_vertices = g->n;
+  if (n_edges) *n_edges = g->m;
+  if (device_bytes) *device_bytes = (int64_t)g->device_bytes();
+  return GC_OK;
+}
+
+extern "C" gc_status gc_graph_edges(gc_graph *g, int32_t *d_u, int32_t *d_v, int64_t cap,
+                                    gc_stream stream) {
+  clear_error();
+  if (!g || (g->m > 0 && (!d_u || !d_v))) {
+    set_error("gc_graph_edges: invalid argument");
+    return GC_EINVAL;
+  }
+  if (cap < g->m) {
+    set_error("gc_graph_edges: cap < m");
+    return GC_ECAPACITY;
+  }
+  return on_device(g, [&]() -> gc_status {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (g->m > 0) {
+      GC_HIP(hipMemcpyAsync(d_u, g->u.ptr, sizeof(int32_t) * g->m, hipMemcpyDeviceToDevice, s));
+      GC_HIP(hipMemcpyAsync(d_v, g->v.ptr, sizeof(int32_t) * g->m, hipMemcpyDeviceToDevice, s));
+    }
+    return GC_OK;
+  });
+}
+
+extern "C" gc_status gc_graph_oriented(gc_graph *g, int32_t *d_rank, int32_t *d_row_ptr,
+                                       int32_t *d_col, int32_t *d_eid, int64_t cap_n,
+                                       int64_t cap_m, gc_stream stream) {
+  clear_error();
+  if (!g) {
+    set_error("gc_graph_oriented: NULL handle");
+    return GC_EINVAL;
+  }
+  if (((d_rank || d_row_ptr) && cap_n < (int64_t)g->n + 1) || ((d_col || d_eid) && cap_m < g->m)) {
+    set_error("gc_graph_oriented: capacity too small");
+    return GC_ECAPACITY;
+  }
+  return on_device(g, [&]() -> gc_status {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t nb = sizeof(int32_t) * (size_t)g->n, mb = sizeof(int32_t) * (size_t)g->m;
+    if (d_rank && nb) GC_HIP(hipMemcpyAsync(d_rank, g->rank.ptr, nb, hipMemcpyDeviceToDevice, s));
+    if (d_row_ptr)
+      GC_HIP(hipMemcpyAsync(d_row_ptr, g->csr.row_ptr.ptr, nb + sizeof(int32_t),
+                            hipMemcpyDeviceToDevice, s));
+    if (d_col && mb) GC_HIP(hipMemcpyAsync(d_col, g->csr.col.ptr, mb, hipMemcpyDeviceToDevice, s));
+    if (d_eid && mb) GC_HIP(hipMemcpyAsync(d_eid, g->csr.eid.ptr, mb, hipMemcpyDeviceToDevice, s));
+    return GC_OK;
+  });
+}
+
+extern "C" gc_status gc_triangle_count(gc_graph *g, gc_stream stream, int64_t *h_count) {
+  clear_error();
+  if (!g || !h_count) {
+    set_error("gc_triangle_count: invalid argument");
+    return GC_EINVAL;
+  }
+  return on_device(g, [&]() -> gc_status {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    *h_count = 0;
+    if (g->m == 0) return GC_OK;
+    const CsrView c = g->csr.view(g->n, (int32_t)g->m);
+    if (!g->units_ready) {
+      GC_TRY(build_units(c, g->units, g->ws, s));
+      g->units_ready = true;
+    }
+    GC_TRY(g->ws.reserve(256));
+    unsigned long long *d = g->ws.take<unsigned long long>(1);
+    GC_HIP(hipMemsetAsync(d, 0, sizeof(unsigned long long), s));
+    GC_TRY(count_triangles(c, g->units, d, s));
+    unsigned long long h = 0;
+    GC_HIP(hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, s));
+    GC_HIP(hipStreamSynchronize(s));
+    *h_count = (int64_t)h;
+    return GC_OK;
+  });
+}
+
+extern "C" gc_status gc_edge_support(gc_graph *g, int32_t *d_support, int64_t cap,
+                                     gc_stream stream) {
+  clear_error();
+  if (!g || (g->m > 0 && !d_support)) {
+    set_error("gc_edge_support: invalid argument");
+    return GC_EINVAL;
+  }
+  if (cap < g->m) {
+    set_error("gc_edge_support: cap < m");
+    return GC_ECAPACITY;
+  }
+  return on_device(g, [&]() -> gc_status {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (g->m == 0) return GC_OK;
+    const int32_t m = (int32_t)g->m;
+    const CsrView c = g->csr.view(g->n, m);
+    if (!g->units_sup_ready) {
+      GC_TRY(build_units_support(c, g->units_sup, g->ws, s));
+      g->units_sup_ready = true;
+    }
+    GC_TRY(dalloc(g->t_sup, sizeof(int32_t) * (size_t)m));
+    int32_t *sup = static_cast<int32_t *>(g->t_sup.ptr);
+    GC_HIP(hipMemsetAsync(sup, 0, sizeof(int32_t) * (size_t)m, s));
+    GC_TRY(slot_support(c, g->units_sup, sup, s));
+    k_slot_to_canonical<<<grid_for(m, 256, 65536), 256, 0, s>>>(sup, c.eid, m, d_support);
+    GC_LAUNCH_CHECK();
+    return GC_OK;
+  });
+}
+
+extern "C" void gc_graph_free(gc_graph *g) {
+  if (!g) return;
+  int prev = 0;
+  bool have_prev = hipGetDevice(&prev) == hipSuccess;
+  if (have_prev && prev != g->device) (void)hipSetDevice(g->device);
+  g->release();
+  if (have_prev && prev != g->device) (void)hipSetDevice(prev);
+  delete g;
+}
+
+extern "C" const char *gc_status_str(gc_status status) {
+  switch (status) {
+    case GC_OK: return "GC_OK";
+    case GC_EINVAL: return "GC_EINVAL: invalid argument";
+    case GC_ERANGE: return "GC_ERANGE: vertex id out of range";
+    case GC_ECAPACITY: return "GC_ECAPACITY: output buffer too small";
+    case GC_ENOMEM: return "GC_ENOMEM: device allocation failed";
+    case GC_EDEVICE: return "GC_EDEVICE: HIP runtime error";
+    case GC_EOVERFLOW: return "GC_EOVERFLOW: size beyond the library's limits";
+    default: return "unknown gc_status";
+  }
+}
+
+extern "C" const char *gc_last_error(void) { return t_last_error.c_str(); }

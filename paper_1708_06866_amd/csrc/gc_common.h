@@ -1,0 +1,151 @@
+// gc_common.h -- internal helpers shared by the libgc HIP sources (not part of
+// the public ABI): status handling, a grow-only device workspace, and
+// wavefront primitives for gfx950 (wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "gc.h"
+
+namespace gc {
+
+// --------------------------------------------------------------------------
+// Status handling
+// --------------------------------------------------------------------------
+void set_error(const std::string &msg);
+void clear_error();
+
+// Evaluate a HIP call; on failure record the message and return GC_EDEVICE
+// (or GC_ENOMEM for allocation failures) from the enclosing function.
+#define GC_HIP(call)                                                        \
+  do {                                                                      \
+    hipError_t e_ = (call);                                                 \
+    if (e_ != hipSuccess) {                                                 \
+      ::gc::set_error(std::string(#call) + ": " + hipGetErrorString(e_));   \
+      return e_ == hipErrorOutOfMemory ? GC_ENOMEM : GC_EDEVICE;            \
+    }                                                                       \
+  } while (0)
+
+// Propagate a gc_status from a helper.
+#define GC_TRY(expr)                 \
+  do {                               \
+    gc_status s_ = (expr);           \
+    if (s_ != GC_OK) return s_;      \
+  } while (0)
+
+// Check the last kernel launch.
+#define GC_LAUNCH_CHECK() GC_HIP(hipGetLastError())
+
+// --------------------------------------------------------------------------
+// Device memory: a tracked allocation and a grow-only bump workspace.
+// --------------------------------------------------------------------------
+struct DeviceBuffer {
+  void *ptr = nullptr;
+  size_t bytes = 0;
+};
+
+gc_status dalloc(DeviceBuffer &b, size_t bytes);  // (re)allocates if too small
+void dfree(DeviceBuffer &b);
+
+// Carves 256-byte aligned sub-buffers out of one allocation.  reserve() grows
+// the backing allocation (only between calls; contents are not preserved).
+struct Workspace {
+  DeviceBuffer buf;
+  size_t off = 0;
+  Workspace() = default;
+  Workspace(const Workspace &) = delete;
+  Workspace &operator=(const Workspace &) = delete;
+  ~Workspace() { dfree(buf); }
+  gc_status reserve(size_t bytes) { off = 0; return dalloc(buf, bytes); }
+  template <class T>
+  T *take(size_t count) {
+    size_t b = (count * sizeof(T) + 255) & ~size_t(255);
+    T *p = reinterpret_cast<T *>(static_cast<char *>(buf.ptr) + off);
+    off += b;
+    return p;
+  }
+};
+
+template <class T>
+inline size_t abytes(size_t count) {
+  return (count * sizeof(T) + 255) & ~size_t(255);
+}
+
+inline int ceil_log2_u64(uint64_t x) {  // smallest b with 2^b >= x
+  int b = 0;
+  while (b < 63 && (uint64_t(1) << b) < x) ++b;
+  return b;
+}
+
+inline unsigned grid_for(int64_t work, int per_block, int64_t cap = 1 << 20) {
+  int64_t g = (work + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+// --------------------------------------------------------------------------
+// Scans and sort (gc_scan.hip, gc_sort.hip)
+// --------------------------------------------------------------------------
+
+// Scratch needed by exclusive_scan for n elements.
+size_t scan_scratch_bytes(int64_t n);
+// out[i] = sum_{j<i} in[i] for i < n, and out[n] = total (out holds n+1).
+// In-place (out == in) is allowed.  n < 2^31, total < 2^31.
+gc_status exclusive_scan(const int32_t *in, int32_t *out, int64_t n,
+                         void *scratch, hipStream_t s);
+
+// Scratch needed by radix_sort for n keys.
+size_t sort_scratch_bytes(int64_t n);
+// Stable LSD radix sort of keys (and optional 32-bit payload) on their low
+// `bits` bits.  keys/alt (and vals/valt) are ping-pong buffers of n entries;
+// on return *keys_out / *vals_out point at whichever buffer holds the result.
+gc_status radix_sort(uint64_t *keys, uint64_t *alt, uint32_t *vals,
+                     uint32_t *valt, int64_t n, int bits, void *scratch,
+                     hipStream_t s, uint64_t **keys_out, uint32_t **vals_out);
+
+// --------------------------------------------------------------------------
+// Wavefront primitives (wave64)
+// --------------------------------------------------------------------------
+#ifdef __HIP_DEVICE_COMPILE__
+#define GC_DEVICE_INLINE __device__ __forceinline__
+#else
+#define GC_DEVICE_INLINE __device__ inline
+#endif
+
+// Sum over the 64 lanes with DPP row operations, then the two cross-row
+// broadcasts; every active lane must participate.  Result returned to all
+// lanes via readlane 63.
+GC_DEVICE_INLINE int32_t wave_sum_i32(int32_t v) {
+  // within quads
+  v += __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+  v += __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+  // within rows of 16
+  v += __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+  v += __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false);  // row_mirror
+  // across rows: lane 15 of row r -> row r+1, then lane 31 -> rows 2, 3
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);  // row_bcast15
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);  // row_bcast31
+  return __builtin_amdgcn_readlane(v, 63);
+}
+
+GC_DEVICE_INLINE uint64_t lanemask_lt() {
+  const unsigned lane = __lane_id();
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Inclusive scan over the wave (shuffles).
+GC_DEVICE_INLINE int32_t wave_inclusive_scan(int32_t v) {
+  const int lane = __lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int32_t t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+}  // namespace gc

@@ -1,0 +1,104 @@
+// gc_graph.h -- the handle behind gc_graph* and the device views the counting
+// and truss kernels take (internal; not part of the public ABI).
+#pragma once
+
+#include "gc_common.h"
+
+namespace gc {
+
+// Degree-oriented CSR over ranks, plus the in-edge index the "stage the middle
+// vertex" schedule walks.  For oriented slot p (edge r -> col[p], r = src[p]):
+//   tail(p) = [p + 1, row_ptr[r + 1])   the part of N+(r) above col[p]
+// and the in-list of vertex x lists, for every slot p with col[p] = x, the
+// range tail(p) packed as int2 {p + 1, row_end}; in_slot[j] is p itself.
+struct CsrView {
+  int32_t n = 0;
+  int32_t m = 0;
+  const int32_t *row_ptr = nullptr;  // [n+1]
+  const int32_t *col = nullptr;      // [m]
+  const int32_t *src = nullptr;      // [m]
+  const int32_t *eid = nullptr;      // [m]
+  const int32_t *in_ptr = nullptr;   // [n+1]
+  const int2 *in_tail = nullptr;     // [m]
+  const int32_t *in_slot = nullptr;  // [m]
+};
+
+// Owned device arrays of one oriented CSR (base graph or a k-truss working
+// copy).
+struct CsrStore {
+  DeviceBuffer row_ptr, col, src, eid, in_ptr, in_tail, in_slot;
+  CsrView view(int32_t n, int32_t m) const {
+    CsrView v;
+    v.n = n;
+    v.m = m;
+    v.row_ptr = static_cast<const int32_t *>(row_ptr.ptr);
+    v.col = static_cast<const int32_t *>(col.ptr);
+    v.src = static_cast<const int32_t *>(src.ptr);
+    v.eid = static_cast<const int32_t *>(eid.ptr);
+    v.in_ptr = static_cast<const int32_t *>(in_ptr.ptr);
+    v.in_tail = static_cast<const int2 *>(in_tail.ptr);
+    v.in_slot = static_cast<const int32_t *>(in_slot.ptr);
+    return v;
+  }
+  void release() {
+    dfree(row_ptr); dfree(col); dfree(src); dfree(eid);
+    dfree(in_ptr); dfree(in_tail); dfree(in_slot);
+  }
+  size_t bytes() const {
+    return row_ptr.bytes + col.bytes + src.bytes + eid.bytes + in_ptr.bytes +
+           in_tail.bytes + in_slot.bytes;
+  }
+};
+
+// Per-bin work-unit lists for the counting kernels (built from a CsrView).
+struct UnitStore {
+  DeviceBuffer units;  // int4 {v, in_begin, in_end, bin}
+  int64_t bin_begin[8] = {0};
+  int64_t bin_count[8] = {0};
+};
+
+}  // namespace gc
+
+struct gc_graph {
+  int device = 0;
+  int32_t n = 0;
+  int64_t m = 0;
+  int bits = 1;  // bits per vertex id: 2^bits >= n
+  gc::DeviceBuffer u, v, rank;
+  gc::CsrStore csr;
+  gc::UnitStore units;      // count-kernel work units of the base CSR
+  bool units_ready = false;
+  gc::UnitStore units_sup;  // support-kernel work units of the base CSR
+  bool units_sup_ready = false;
+  gc::Workspace ws;         // scratch for counting / truss calls
+  gc::CsrStore work[2];     // k-truss ping-pong working CSRs
+  gc::UnitStore work_units;
+  gc::DeviceBuffer t_sup, t_flag, t_pos, t_misc;  // k-truss round state
+  size_t device_bytes() const {
+    return u.bytes + v.bytes + rank.bytes + csr.bytes() + units.units.bytes +
+           units_sup.units.bytes + ws.buf.bytes + work[0].bytes() + work[1].bytes() +
+           work_units.units.bytes + t_sup.bytes + t_flag.bytes + t_pos.bytes + t_misc.bytes;
+  }
+  void release() {
+    gc::dfree(u); gc::dfree(v); gc::dfree(rank);
+    csr.release(); work[0].release(); work[1].release();
+    gc::dfree(units.units); gc::dfree(units_sup.units); gc::dfree(work_units.units);
+    gc::dfree(t_sup); gc::dfree(t_flag); gc::dfree(t_pos); gc::dfree(t_misc);
+    gc::dfree(ws.buf);
+  }
+};
+
+namespace gc {
+
+// Internal entry points shared between translation units.
+// (gc_build.hip)
+gc_status build_in_lists(int32_t n, int32_t m, int bits, CsrStore &c, Workspace &ws,
+                         hipStream_t s);
+// (gc_count.hip)
+gc_status build_units(const CsrView &c, UnitStore &u, Workspace &ws, hipStream_t s);
+gc_status build_units_support(const CsrView &c, UnitStore &u, Workspace &ws, hipStream_t s);
+gc_status count_triangles(const CsrView &c, const UnitStore &u, unsigned long long *d_count,
+                          hipStream_t s);
+gc_status slot_support(const CsrView &c, const UnitStore &u, int32_t *d_sup, hipStream_t s);
+
+}  // namespace gc

@@ -1,0 +1,82 @@
+"""The C ABI library loads and exports every function include/gc.h declares;
+host-side argument checks answer without touching a GPU.  CPU only."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gc.h")
+LIB = os.path.join(ROOT, "paper_1708_06866_amd", "libgc.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gc_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_1708_06866_amd import build
+        build.build()
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_core_calls():
+    names = declared_functions()
+    for core in ("gc_build_csr", "gc_triangle_count", "gc_edge_support", "gc_ktruss",
+                 "gc_truss_decomposition", "gc_graph_free", "gc_last_error"):
+        assert core in names
+
+
+def test_every_declared_symbol_exported(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_status_strings(lib):
+    lib.gc_status_str.restype = ctypes.c_char_p
+    lib.gc_status_str.argtypes = [ctypes.c_int32]
+    for st in range(-6, 1):
+        assert lib.gc_status_str(st).decode().startswith("GC_")
+    assert b"unknown" in lib.gc_status_str(-99)
+
+
+def test_host_argument_checks(lib):
+    P = ctypes.c_void_p
+    lib.gc_build_csr.argtypes = [P, P, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32, P,
+                                 ctypes.POINTER(P)]
+    lib.gc_build_csr.restype = ctypes.c_int32
+    lib.gc_last_error.restype = ctypes.c_char_p
+    out = P(1234)
+    # NULL out
+    assert lib.gc_build_csr(None, None, 0, 1, 0, None, None) == -1
+    # negative pair count; *out is cleared
+    assert lib.gc_build_csr(None, None, -1, 1, 0, None, ctypes.byref(out)) == -1
+    assert not out.value
+    # unknown flag
+    assert lib.gc_build_csr(None, None, 0, 1, 0x80, None, ctypes.byref(out)) == -1
+    # pairs but NULL arrays
+    assert lib.gc_build_csr(None, None, 5, 10, 0, None, ctypes.byref(out)) == -1
+    # too many pairs
+    assert lib.gc_build_csr(P(8), P(8), 1 << 31, 10, 0, None, ctypes.byref(out)) == -6
+    # pairs on an empty vertex set
+    assert lib.gc_build_csr(P(8), P(8), 3, 0, 0, None, ctypes.byref(out)) == -2
+    assert len(lib.gc_last_error()) > 0
+    for fn, args in (("gc_triangle_count", [None, None, None]),
+                     ("gc_ktruss", [None, 3, None, 0, None, None]),
+                     ("gc_truss_decomposition", [None, None, 0, None, None])):
+        f = getattr(lib, fn)
+        f.restype = ctypes.c_int32
+        assert f(*args) == -1
+
+
+def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
+    import paper_1708_06866_amd as gc
+    monkeypatch.setattr(gc, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(gc, "_lib", None)
+    with pytest.raises(ImportError):
+        gc.lib()

@@ -1,0 +1,288 @@
+"""GPU parity: libgc (through its C ABI) against the CPU oracle, bit-exact.
+
+Every input is seeded and synthetic.  Small and medium graphs are checked
+against the oracle run in the test; the larger seeded workloads against the
+oracle digests in tests/golden/digests.json (written by make_digests.py from
+oracle/ alone).  All results are integers: tolerance 0.
+"""
+import hashlib
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1708_06866_amd as gc  # noqa: E402
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "digests.json")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def sha(a):
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+def check_all(src, dst, n, label, ks=None, decomposition=True, one_based=False):
+    """Build on the GPU and compare edges, T, support, k-truss and truss numbers
+    with the oracle."""
+    say("case", label, "pairs", len(src), "n", n)
+    g = gc.build_graph(src, dst, n, one_based=one_based)
+    u, v = oracle.normalise(src, dst, n, one_based=one_based)
+    gu, gv = g.edges()
+    assert np.array_equal(gu.cpu().numpy(), u), label
+    assert np.array_equal(gv.cpu().numpy(), v), label
+    assert g.m == len(u)
+    T = g.triangle_count()
+    assert T == oracle.triangle_count(n, u, v), label
+    sup = g.edge_support().cpu().numpy()
+    sup_ref = oracle.support(n, u, v, "listing")
+    assert np.array_equal(sup, sup_ref), label
+    assert int(sup.astype(np.int64).sum()) == 3 * T
+    if decomposition:
+        tau, kmax = g.truss_decomposition()
+        tau_ref, kmax_ref = oracle.truss_decomposition(n, u, v, "peel")
+        assert kmax == kmax_ref, (label, kmax, kmax_ref)
+        assert np.array_equal(tau.cpu().numpy(), tau_ref), label
+        if ks is None:
+            ks = sorted(set([2, 3, 4, kmax, kmax + 1]) - {0, 1})
+        for k in ks:
+            mask, mk = g.ktruss(k)
+            ref = (tau_ref >= k).astype(np.uint8) if k >= 2 else None
+            assert np.array_equal(mask.cpu().numpy(), ref), (label, k)
+            assert mk == int(ref.sum())
+    g.free()
+    return T
+
+
+# ----------------------------------------------------------------------------
+# closed forms and the paper's examples
+# ----------------------------------------------------------------------------
+
+CLOSED = {
+    "diamond_fig1": gg.diamond(),
+    "K1": gg.complete(1), "K2": gg.complete(2), "K3": gg.complete(3), "K5": gg.complete(5),
+    "K40": gg.complete(40),
+    "tripartite_2_3_5": gg.complete_tripartite(2, 3, 5),
+    "tripartite_6_7_9": gg.complete_tripartite(6, 7, 9),
+    "king_2": gg.king(2), "king_16": gg.king(16), "king_64": gg.king(64),
+    "wheel_9": gg.wheel(9), "windmill_50": gg.windmill(50), "book_7": gg.book(7),
+    "star_300": gg.star(300), "path_50": gg.path(50), "cycle_17": gg.cycle(17),
+    "tree_500": gg.random_tree(500, seed=3), "bipartite_20_30": gg.complete_bipartite(20, 30),
+    "union": gg.disjoint_union(gg.complete(12), gg.king(8), gg.wheel(6), gg.book(4)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CLOSED))
+def test_closed_forms(name):
+    src, dst, n = CLOSED[name]
+    check_all(src, dst, n, name)
+
+
+def test_table2_king_256_closed_form():
+    """Table II, n = 8: 65,536 vertices, 260,610 edges, 4(M-1)^2 triangles
+    (the printed column is twice that); the whole graph is a 4-truss."""
+    src, dst, n = gg.king(256)
+    g = gc.build_graph(src, dst, n)
+    assert g.m == 260610
+    assert g.triangle_count() == 4 * 255 ** 2 == 520200 // 2
+    tau, kmax = g.truss_decomposition()
+    assert kmax == 4 and bool((tau == 4).all())
+    g.free()
+
+
+# ----------------------------------------------------------------------------
+# R-MAT scale 10 (the CPU-fast configuration), seeds 1..8
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(1, 9))
+def test_rmat_scale10(seed):
+    src, dst, n = gg.rmat(10, 16, seed=seed)
+    check_all(src, dst, n, "rmat10 seed %d" % seed, ks=list(range(2, 40)))
+
+
+def test_rmat_presentation_invariance():
+    src, dst, n = gg.rmat(11, 16, seed=5)
+    s2, d2, _ = gg.scramble(src, dst, n, seed=6)
+    T1 = check_all(src, dst, n, "rmat11")
+    T2 = check_all(s2, d2, n, "rmat11 scrambled")
+    s3, d3, _, _ = gg.relabel(src, dst, n, seed=7)
+    T3 = check_all(s3, d3, n, "rmat11 relabelled")
+    T4 = check_all(src + 1, dst + 1, n, "rmat11 one-based", one_based=True)
+    assert T1 == T2 == T3 == T4
+
+
+@pytest.mark.parametrize("scale", [12, 14, 16])
+def test_rmat_medium(scale):
+    src, dst, n = gg.rmat(scale, 16, seed=1)
+    check_all(src, dst, n, "rmat%d" % scale, ks=[3, 4, 5, 6])
+
+
+def test_er_and_rgg():
+    check_all(*gg.er(1 << 14, 16 << 14, seed=2), "er14")
+    check_all(*gg.rgg(1 << 13, 20.0, seed=3), "rgg13")
+
+
+# ----------------------------------------------------------------------------
+# degree-bin boundaries, long in-lists, skew
+# ----------------------------------------------------------------------------
+
+def _complete_checks(nk):
+    src, dst, n = gg.complete(nk)
+    say("case complete", nk)
+    g = gc.build_graph(src, dst, n)
+    assert g.m == nk * (nk - 1) // 2
+    assert g.triangle_count() == nk * (nk - 1) * (nk - 2) // 6
+    sup = g.edge_support()
+    assert bool((sup == nk - 2).all())
+    mask, mk = g.ktruss(nk)
+    assert mk == g.m
+    mask, mk = g.ktruss(nk + 1)
+    assert mk == 0
+    tau, kmax = g.truss_decomposition()
+    assert kmax == nk and bool((tau == nk).all())
+    g.free()
+
+
+@pytest.mark.parametrize("nk", [33, 34, 257, 258, 2049, 2050, 4098])
+def test_complete_graph_bins(nk):
+    """K_n has out-degrees 0..n-1 in any orientation, so it reaches every bin
+    up to n-1, including the edges of each bin's limit."""
+    _complete_checks(nk)
+
+
+def test_complete_graph_global_search_bin():
+    """Out-lists longer than the largest LDS table (binary search in HBM)."""
+    _complete_checks(8200)
+
+
+@pytest.mark.parametrize("p", [127, 128, 129, 5000])
+def test_book_long_in_lists(p):
+    """Hub vertices with in-lists around and far above one work unit."""
+    src, dst, n = gg.book(p)
+    check_all(src, dst, n, "book %d" % p)
+
+
+def test_star_of_cliques_skew():
+    parts = [gg.complete(30)] * 20 + [gg.star(3000)]
+    src, dst, n = gg.disjoint_union(*parts)
+    # join every clique's vertex 0 to the star centre (heavy hub)
+    extra_s = np.arange(20, dtype=np.int32) * 30
+    extra_d = np.full(20, 20 * 30, dtype=np.int32)
+    check_all(np.concatenate([src, extra_s]), np.concatenate([dst, extra_d]), n, "skew")
+
+
+# ----------------------------------------------------------------------------
+# empty and degenerate inputs, errors
+# ----------------------------------------------------------------------------
+
+def test_empty_inputs():
+    e = np.zeros(0, np.int32)
+    for n in (0, 1, 10):
+        g = gc.build_graph(e, e, n)
+        assert g.m == 0 and g.triangle_count() == 0
+        assert g.edge_support().numel() == 0
+        mask, mk = g.ktruss(3)
+        assert mk == 0
+        tau, kmax = g.truss_decomposition()
+        assert kmax == 0 and tau.numel() == 0
+        g.free()
+    loops = np.array([3, 3, 5], np.int32)
+    g = gc.build_graph(loops, loops, 10)
+    assert g.m == 0 and g.truss_decomposition()[1] == 0
+    g.free()
+    g = gc.build_graph(np.array([1, 0, 1], np.int32), np.array([0, 1, 0], np.int32), 2)
+    assert g.m == 1 and g.triangle_count() == 0
+    tau, kmax = g.truss_decomposition()
+    assert kmax == 2 and tau.tolist() == [2]
+    assert g.ktruss(2)[1] == 1 and g.ktruss(3)[1] == 0
+    g.free()
+
+
+def test_errors_are_reported():
+    with pytest.raises(gc.GCError) as ei:
+        gc.build_graph(np.array([0, 5], np.int32), np.array([1, 2], np.int32), 5)
+    assert ei.value.status == gc.GC_ERANGE
+    with pytest.raises(gc.GCError) as ei:
+        gc.build_graph(np.array([0, 1], np.int32), np.array([1, 2], np.int32), 5, one_based=True)
+    assert ei.value.status == gc.GC_ERANGE
+    g = gc.build_graph(*gg.complete(5)[:2], 5)
+    with pytest.raises(gc.GCError) as ei:
+        g.ktruss(1)
+    assert ei.value.status == gc.GC_EINVAL
+    small = torch.empty(3, dtype=torch.int32, device="cuda")
+    with pytest.raises(gc.GCError) as ei:
+        g.edge_support(out=small)
+    assert ei.value.status == gc.GC_ECAPACITY
+    assert g.triangle_count() == 10   # handle still usable after errors
+    g.free()
+
+
+def test_repeat_runs_identical():
+    src, dst, n = gg.rmat(13, 16, seed=9)
+    g = gc.build_graph(src, dst, n)
+    a = (g.triangle_count(), g.edge_support().cpu().numpy(), g.truss_decomposition()[0].cpu().numpy())
+    for _ in range(2):
+        b = (g.triangle_count(), g.edge_support().cpu().numpy(),
+             g.truss_decomposition()[0].cpu().numpy())
+        assert a[0] == b[0] and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+    g.free()
+    g2 = gc.build_graph(src, dst, n)
+    assert g2.triangle_count() == a[0]
+    g2.free()
+
+
+# ----------------------------------------------------------------------------
+# larger seeded workloads against stored oracle digests
+# ----------------------------------------------------------------------------
+
+def _golden():
+    if not os.path.exists(GOLDEN):
+        return {}
+    with open(GOLDEN) as f:
+        return json.load(f)
+
+
+DIGEST_GENS = {
+    "rmat_s16_ef16_seed1": lambda: gg.rmat(16, 16, seed=1),
+    "rmat_s18_ef16_seed1": lambda: gg.rmat(18, 16, seed=1),
+    "rmat_s20_ef16_seed1": lambda: gg.rmat(20, 16, seed=1),
+    "er_n20_m16n_seed2": lambda: gg.er(1 << 20, 16 << 20, seed=2),
+}
+
+
+@pytest.mark.parametrize("name", sorted(DIGEST_GENS))
+def test_against_oracle_digest(name):
+    gold = _golden().get(name)
+    if gold is None:
+        pytest.skip("no stored oracle digest for %s" % name)
+    say("case digest", name)
+    src, dst, n = DIGEST_GENS[name]()
+    g = gc.build_graph(src, dst, n)
+    assert g.m == gold["m"]
+    u, v = g.edges()
+    assert sha(torch.stack([u, v], 1).cpu().numpy()) == gold["edges_sha256"]
+    assert g.triangle_count() == gold["triangles"]
+    assert sha(g.edge_support().cpu().numpy().astype("<i4")) == gold["support_sha256"]
+    if "kmax" in gold:
+        tau, kmax = g.truss_decomposition()
+        assert kmax == gold["kmax"]
+        assert sha(tau.cpu().numpy().astype("<i4")) == gold["truss_sha256"]
+        for k, rec in gold["ktruss"].items():
+            mask, mk = g.ktruss(int(k))
+            assert mk == rec["m_k"]
+            assert sha(mask.cpu().numpy()) == rec["mask_sha256"]
+    g.free()

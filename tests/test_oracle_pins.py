@@ -386,3 +386,23 @@ def test_mutation_would_be_caught():
     assert oracle.triangle_count(n, u, v) == 0
     n, u, v = canon(*gg.complete_bipartite(3, 3))
     assert oracle.triangle_count(n, u, v) == 0
+
+
+# --------------------------------------------------------------------------
+# the two support routes and the two truss routes agree
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_support_listing_equals_definition(seed):
+    for g in (gg.rmat(11, 16, seed=seed), gg.er(2000, 40000, seed=seed),
+              gg.rgg(1500, 20.0, seed=seed), gg.complete(25), gg.king(9)):
+        n, u, v = canon(*g)
+        assert np.array_equal(oracle.support(n, u, v, "listing"),
+                              oracle.support(n, u, v, "definition"))
+
+
+def test_ktruss_bulk_equals_peel_rmat():
+    n, u, v = canon(*gg.rmat(10, 16, seed=4))
+    for k in (3, 4, 6, 9, 15):
+        bulk, _ = oracle.ktruss(n, u, v, k, "bulk")
+        assert np.array_equal(bulk, oracle.ktruss(n, u, v, k, "peel"))
