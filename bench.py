@@ -154,9 +154,10 @@ def main():
 
     # warmup
     recs = []
-    for _ in range(args.warmup):
+    for i in range(args.warmup):
         g = step(recs)
         g.free()
+        log("warmup step %d done" % i)
     torch.cuda.synchronize()
 
     # algorithmic bytes of the count pass (host-side, outside the timed region)
@@ -170,9 +171,10 @@ def main():
     recs = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for i in range(args.steps):
         g = step(recs)
         g.free()
+        log("step %d done" % i)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 

@@ -100,5 +100,8 @@ gc_status build_units_support(const CsrView &c, UnitStore &u, Workspace &ws, hip
 gc_status count_triangles(const CsrView &c, const UnitStore &u, unsigned long long *d_count,
                           hipStream_t s);
 gc_status slot_support(const CsrView &c, const UnitStore &u, int32_t *d_sup, hipStream_t s);
+// (gc_peel.hip) truss numbers by peeling with incremental support updates;
+// tau must hold m entries.
+gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStream_t s);
 
 }  // namespace gc

@@ -14,6 +14,9 @@
 // a recount the next level starts from min-support + 3: every level in between
 // removes nothing.  An edge dropped while working on level k has truss number
 // k - 1.
+#include <stdlib.h>
+#include <string.h>
+
 #include "gc_graph.h"
 
 namespace gc {
@@ -257,7 +260,22 @@ extern "C" gc_status gc_truss_decomposition(gc_graph *g, int32_t *d_truss, int64
   int prev = 0;
   GC_HIP(hipGetDevice(&prev));
   if (prev != g->device) GC_HIP(hipSetDevice(g->device));
-  gc_status st = decomposition_impl(g, d_truss, h_kmax, static_cast<hipStream_t>(stream));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  gc_status st;
+  const char *method = getenv("GC_TRUSS_METHOD");
+  if (method && strcmp(method, "rounds") == 0) {
+    st = decomposition_impl(g, d_truss, h_kmax, s);
+  } else {
+    DeviceBuffer own;
+    int32_t *tau = d_truss;
+    st = GC_OK;
+    if (!tau && g->m > 0) {
+      st = dalloc(own, sizeof(int32_t) * (size_t)g->m);
+      tau = static_cast<int32_t *>(own.ptr);
+    }
+    if (st == GC_OK) st = decomposition_peel(g, tau, h_kmax, s);
+    dfree(own);
+  }
   if (prev != g->device) (void)hipSetDevice(prev);
   return st;
 }

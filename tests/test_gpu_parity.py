@@ -286,3 +286,20 @@ def test_against_oracle_digest(name):
             assert mk == rec["m_k"]
             assert sha(mask.cpu().numpy()) == rec["mask_sha256"]
     g.free()
+
+
+def test_decomposition_peel_equals_rounds(monkeypatch):
+    """Incremental peeling and recompute-per-round give the same truss numbers."""
+    for label, (src, dst, n) in (("rmat14", gg.rmat(14, 16, seed=3)),
+                                 ("rgg12", gg.rgg(1 << 12, 20.0, seed=4)),
+                                 ("K60", gg.complete(60))):
+        say("case decomposition methods", label)
+        g = gc.build_graph(src, dst, n)
+        monkeypatch.setenv("GC_TRUSS_METHOD", "rounds")
+        t_rounds, k_rounds = g.truss_decomposition()
+        t_rounds = t_rounds.cpu().numpy()
+        monkeypatch.setenv("GC_TRUSS_METHOD", "peel")
+        t_peel, k_peel = g.truss_decomposition()
+        assert k_rounds == k_peel
+        assert np.array_equal(t_rounds, t_peel.cpu().numpy())
+        g.free()
