@@ -108,6 +108,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-decomposition", action="store_true",
                     help="step = build + count only")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run one elementwise int32 kernel over 1 GiB (reads 1 GiB, "
+                         "writes 1 GiB) so HBM counters can be scaled against known bytes")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -122,6 +125,15 @@ def main():
         sys.exit(2)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+
+    if args.copy_calibration:
+        x = torch.ones(1 << 28, dtype=torch.int32, device=dev)
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        torch.neg(x, out=y)
+        torch.cuda.synchronize()
+        log("copy calibration: elementwise kernel read %d B, wrote %d B" % (x.numel() * 4, y.numel() * 4))
+        del x, y
 
     t = time.perf_counter()
     src, dst, n = gen_inputs(args.workload, args.scale, args.ef, args.seed)

@@ -132,6 +132,70 @@ gc_status gc_ktruss(gc_graph *g, int32_t k, uint8_t *d_in_truss, int64_t cap,
 gc_status gc_truss_decomposition(gc_graph *g, int32_t *d_truss, int64_t cap,
                                  gc_stream stream, int32_t *h_kmax);
 
+/* ------------------------------------------------------------------------ */
+/* Batches: many independent graphs counted in one launch per degree bin.    */
+/* ------------------------------------------------------------------------ */
+typedef struct gc_batch gc_batch;
+
+/* Build one device structure for G independent graphs.  Graph g's raw pairs
+ * are d_src/d_dst[h_pair_off[g] .. h_pair_off[g+1]) (device, int32; host
+ * offsets, h_pair_off[0] = 0, non-decreasing) with ids in [0, h_nv[g]) (or
+ * 1..h_nv[g] with GC_INPUT_ONE_BASED); each graph is normalised as in
+ * gc_build_csr.  The graphs become one disjoint union, so the per-graph
+ * results of every operation below are those of the graphs taken alone
+ * (Sec. III definitions apply graph by graph).  Synchronises `stream`.
+ * GC_ERANGE if an id falls outside its own graph. */
+gc_status gc_batch_build(const int32_t *d_src, const int32_t *d_dst,
+                         const int64_t *h_pair_off, const int32_t *h_nv,
+                         int32_t G, uint32_t flags, gc_stream stream,
+                         gc_batch **out);
+
+/* Number of graphs, total canonical edges over all graphs, device bytes. */
+gc_status gc_batch_info(const gc_batch *b, int32_t *n_graphs, int64_t *n_edges,
+                        int64_t *device_bytes);
+
+/* h_off[0..G] (host): the canonical edges of graph g are positions
+ * [h_off[g], h_off[g+1]) of every per-edge batch output, in graph g's own
+ * canonical order. */
+gc_status gc_batch_edge_offsets(const gc_batch *b, int64_t *h_off);
+
+/* The union graph behind a batch (owned by the batch; do not free).  Any
+ * gc_graph call may be applied to it. */
+gc_graph *gc_batch_graph(gc_batch *b);
+
+/* Per-graph triangle counts (Sec. III-A) into d_T[0..G) (device, int64).
+ * The zeroing and the per-bin count launches are captured into a HIP graph on
+ * the first call and replayed afterwards.  Stream-ordered, no host sync. */
+gc_status gc_batch_triangle_count(gc_batch *b, int64_t *d_T, gc_stream stream);
+
+/* Per-edge support (Sec. III-B) of all graphs into d_support (device, int32,
+ * Σm entries, batch edge order).  cap < Σm gives GC_ECAPACITY. */
+gc_status gc_batch_edge_support(gc_batch *b, int32_t *d_support, int64_t cap,
+                                gc_stream stream);
+
+/* k-truss of every graph (Sec. III-B, Alg. 4): d_mask[e] in batch edge order
+ * (device, uint8, Σm entries) and d_mk[g] = edges in graph g's k-truss
+ * (device, int64, G entries).  Synchronises `stream`. */
+gc_status gc_batch_ktruss(gc_batch *b, int32_t k, uint8_t *d_mask, int64_t cap,
+                          int64_t *d_mk, gc_stream stream);
+
+/* Autotuner: for each degree bin that has work, time every admissible count
+ * strategy on this batch (0: LDS hash, load <= 1/2; 1: LDS hash, load <= 1/4;
+ * 2: binary search in HBM) and keep the fastest.  h_strategy[5] (host, may
+ * be NULL) receives the choices, h_ms[5*3] (may be NULL) the mean times in ms
+ * (-1 where not run).  If the environment variable GC_AUTOTUNE_CACHE names a
+ * file, choices are written there and read back by later gc_batch_build calls
+ * (lines "<arch> <bin> <strategy>").  Results never depend on the choice. */
+gc_status gc_batch_autotune(gc_batch *b, gc_stream stream, int32_t *h_strategy,
+                            float *h_ms);
+
+/* Force the count strategy of each of the 5 bins (GC_EINVAL if a strategy is
+ * not admissible for its bin; the last bin admits only 2). */
+gc_status gc_batch_set_strategy(gc_batch *b, const int32_t *h_strategy);
+
+/* Release a batch and its union graph (NULL is a no-op). */
+void gc_batch_free(gc_batch *b);
+
 /* Release a handle and its device memory (NULL is a no-op). */
 void gc_graph_free(gc_graph *g);
 

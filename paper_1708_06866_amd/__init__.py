@@ -67,9 +67,25 @@ def lib():
         L.gc_status_str.restype = ctypes.c_char_p
         L.gc_last_error.argtypes = []
         L.gc_last_error.restype = ctypes.c_char_p
+        L.gc_batch_build.argtypes = [P, P, P, P, i32, u32, P, ctypes.POINTER(P)]
+        L.gc_batch_info.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i64),
+                                    ctypes.POINTER(i64)]
+        L.gc_batch_edge_offsets.argtypes = [P, P]
+        L.gc_batch_graph.argtypes = [P]
+        L.gc_batch_graph.restype = P
+        L.gc_batch_triangle_count.argtypes = [P, P, P]
+        L.gc_batch_edge_support.argtypes = [P, P, i64, P]
+        L.gc_batch_ktruss.argtypes = [P, i32, P, i64, P, P]
+        L.gc_batch_autotune.argtypes = [P, P, P, P]
+        L.gc_batch_set_strategy.argtypes = [P, P]
+        L.gc_batch_free.argtypes = [P]
+        L.gc_batch_free.restype = None
         for name in ("gc_build_csr", "gc_graph_info", "gc_graph_edges", "gc_graph_oriented",
                      "gc_triangle_count", "gc_edge_support", "gc_ktruss",
-                     "gc_truss_decomposition"):
+                     "gc_truss_decomposition", "gc_batch_build", "gc_batch_info",
+                     "gc_batch_edge_offsets", "gc_batch_triangle_count",
+                     "gc_batch_edge_support", "gc_batch_ktruss", "gc_batch_autotune",
+                     "gc_batch_set_strategy"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -181,7 +197,7 @@ def gc_build_csr(src: torch.Tensor, dst: torch.Tensor, n_vertices: int, flags: i
 
 
 def gc_graph_info(g):
-    return g.info() if isinstance(g, Graph) else Graph(g, None).info()
+    return g.info()
 
 
 def gc_graph_edges(g: Graph, stream=None):
@@ -244,3 +260,119 @@ def build_graph(src, dst, n_vertices: int, device="cuda", one_based: bool = Fals
     s = torch.as_tensor(src, dtype=torch.int32).to(device)
     d = torch.as_tensor(dst, dtype=torch.int32).to(device)
     return gc_build_csr(s, d, n_vertices, GC_INPUT_ONE_BASED if one_based else 0)
+
+
+# ----------------------------------------------------------------------------
+# batches
+# ----------------------------------------------------------------------------
+import numpy as _np  # noqa: E402
+
+
+class Batch:
+    """Owning wrapper of a gc_batch* (many graphs, one device structure)."""
+
+    def __init__(self, handle, device):
+        self._h = handle
+        self.device = device
+        n_graphs, m, _ = self.info()
+        self.n_graphs = n_graphs
+        off = _np.zeros(n_graphs + 1, dtype=_np.int64)
+        _check(lib().gc_batch_edge_offsets(self.handle, ctypes.c_void_p(off.ctypes.data)),
+               "gc_batch_edge_offsets")
+        self.edge_offsets = off
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("batch already freed")
+        return self._h
+
+    def free(self):
+        if self._h:
+            lib().gc_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def info(self):
+        g, m, b = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().gc_batch_info(self.handle, ctypes.byref(g), ctypes.byref(m), ctypes.byref(b)),
+               "gc_batch_info")
+        return int(g.value), int(m.value), int(b.value)
+
+    def graph(self) -> Graph:
+        """The union graph (owned by the batch: do not free it)."""
+        g = Graph(ctypes.c_void_p(lib().gc_batch_graph(self.handle)), self.device)
+        g.free = lambda: None  # the batch owns it
+        return g
+
+    def triangle_count(self, out=None, stream=None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(max(self.n_graphs, 1), dtype=torch.int64, device=self.device)
+        _check(lib().gc_batch_triangle_count(self.handle, _ptr(out), _stream(stream)),
+               "gc_batch_triangle_count")
+        return out[:self.n_graphs]
+
+    def edge_support(self, out=None, stream=None) -> torch.Tensor:
+        m = int(self.edge_offsets[-1])
+        if out is None:
+            out = torch.empty(max(m, 1), dtype=torch.int32, device=self.device)
+        _check(lib().gc_batch_edge_support(self.handle, _ptr(out), out.numel(), _stream(stream)),
+               "gc_batch_edge_support")
+        return out[:m]
+
+    def ktruss(self, k: int, stream=None):
+        m = int(self.edge_offsets[-1])
+        mask = torch.empty(max(m, 1), dtype=torch.uint8, device=self.device)
+        mk = torch.empty(max(self.n_graphs, 1), dtype=torch.int64, device=self.device)
+        _check(lib().gc_batch_ktruss(self.handle, int(k), _ptr(mask), mask.numel(), _ptr(mk),
+                                     _stream(stream)), "gc_batch_ktruss")
+        return mask[:m], mk[:self.n_graphs]
+
+    def autotune(self, stream=None):
+        st = _np.zeros(5, dtype=_np.int32)
+        ms = _np.zeros(15, dtype=_np.float32)
+        _check(lib().gc_batch_autotune(self.handle, _stream(stream), ctypes.c_void_p(st.ctypes.data),
+                                       ctypes.c_void_p(ms.ctypes.data)), "gc_batch_autotune")
+        return st, ms.reshape(5, 3)
+
+    def set_strategy(self, strategy):
+        st = _np.ascontiguousarray(strategy, dtype=_np.int32)
+        _check(lib().gc_batch_set_strategy(self.handle, ctypes.c_void_p(st.ctypes.data)),
+               "gc_batch_set_strategy")
+
+
+def gc_batch_build(src: torch.Tensor, dst: torch.Tensor, pair_offsets, n_vertices,
+                   flags: int = 0, stream=None) -> Batch:
+    """src/dst: concatenated raw pairs (int32, cuda); pair_offsets: G+1 host
+    offsets; n_vertices: G vertex counts."""
+    src = _dev_i32(src, "src")
+    dst = _dev_i32(dst, "dst")
+    off = _np.ascontiguousarray(pair_offsets, dtype=_np.int64)
+    nv = _np.ascontiguousarray(n_vertices, dtype=_np.int32)
+    G = len(nv)
+    if len(off) != G + 1:
+        raise ValueError("pair_offsets must have G+1 entries")
+    if int(off[-1]) != src.numel() or src.numel() != dst.numel():
+        raise ValueError("pair_offsets[-1] must equal the number of pairs")
+    h = ctypes.c_void_p()
+    _check(lib().gc_batch_build(_ptr(src), _ptr(dst), ctypes.c_void_p(off.ctypes.data),
+                                ctypes.c_void_p(nv.ctypes.data), G, int(flags), _stream(stream),
+                                ctypes.byref(h)), "gc_batch_build")
+    return Batch(h, src.device)
+
+
+def build_batch(graphs, device="cuda") -> Batch:
+    """Convenience: list of host (src, dst, n) -> Batch on ``device``."""
+    srcs = [_np.asarray(g[0], dtype=_np.int32) for g in graphs]
+    dsts = [_np.asarray(g[1], dtype=_np.int32) for g in graphs]
+    off = _np.zeros(len(graphs) + 1, dtype=_np.int64)
+    off[1:] = _np.cumsum([len(x) for x in srcs])
+    nv = [int(g[2]) for g in graphs]
+    s = torch.from_numpy(_np.concatenate(srcs) if srcs else _np.zeros(0, _np.int32)).to(device)
+    d = torch.from_numpy(_np.concatenate(dsts) if dsts else _np.zeros(0, _np.int32)).to(device)
+    return gc_batch_build(s, d, off, nv)

@@ -66,12 +66,15 @@ __global__ void k_emit_edges(const uint64_t *__restrict__ keys, int64_t P,
   }
 }
 
+// u is sorted (canonical order): its counts go per run; v takes atomics.
 __global__ void k_degrees(const int32_t *__restrict__ u, const int32_t *__restrict__ v, int64_t m,
                           int32_t *__restrict__ deg) {
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    atomicAdd(&deg[u[e]], 1);
-    atomicAdd(&deg[v[e]], 1);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t span = (m + stride - 1) / stride * stride;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < span; e += stride) {
+    const bool valid = e < m;
+    wave_run_count(valid, valid ? u[e] : 0, deg);
+    if (valid) atomicAdd(&deg[v[e]], 1);
   }
 }
 
@@ -83,11 +86,14 @@ __global__ void k_vertex_keys(const int32_t *__restrict__ deg, int32_t n, int bi
 }
 
 __global__ void k_ranks(const uint64_t *__restrict__ sorted, int32_t n, int bits,
-                        int32_t *__restrict__ rank) {
+                        int32_t *__restrict__ rank, int32_t *__restrict__ vid) {
   const uint64_t mask = (uint64_t(1) << bits) - 1;
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n;
-       r += (int64_t)gridDim.x * blockDim.x)
-    rank[sorted[r] & mask] = (int32_t)r;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t x = (int32_t)(sorted[r] & mask);
+    rank[x] = (int32_t)r;
+    vid[r] = x;
+  }
 }
 
 __global__ void k_orient(const int32_t *__restrict__ u, const int32_t *__restrict__ v, int64_t m,
@@ -102,41 +108,54 @@ __global__ void k_orient(const int32_t *__restrict__ u, const int32_t *__restric
   }
 }
 
+// Keys are sorted by (src, dst): out-degrees are counted per run of src.
 __global__ void k_csr_fill(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ vals,
                            int64_t m, int bits, int32_t *__restrict__ col,
                            int32_t *__restrict__ src, int32_t *__restrict__ eid,
                            int32_t *__restrict__ outdeg) {
   const uint64_t mask = (uint64_t(1) << bits) - 1;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const uint64_t k = keys[i];
-    const int32_t s = (int32_t)(k >> bits);
-    col[i] = (int32_t)(k & mask);
-    src[i] = s;
-    eid[i] = (int32_t)vals[i];
-    atomicAdd(&outdeg[s], 1);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t span = (m + stride - 1) / stride * stride;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < span; i += stride) {
+    const bool valid = i < m;
+    int32_t s = 0;
+    if (valid) {
+      const uint64_t k = keys[i];
+      s = (int32_t)(k >> bits);
+      col[i] = (int32_t)(k & mask);
+      src[i] = s;
+      eid[i] = (int32_t)vals[i];
+    }
+    wave_run_count(valid, s, outdeg);
   }
 }
 
 __global__ void k_in_keys(const int32_t *__restrict__ col, int64_t m, uint64_t *__restrict__ keys,
-                          uint32_t *__restrict__ vals, int32_t *__restrict__ indeg) {
+                          uint32_t *__restrict__ vals) {
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < m;
        p += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t x = col[p];
-    keys[p] = (uint64_t)(uint32_t)x;
+    keys[p] = (uint64_t)(uint32_t)col[p];
     vals[p] = (uint32_t)p;
-    atomicAdd(&indeg[x], 1);
   }
 }
 
-__global__ void k_in_fill(const uint32_t *__restrict__ slots, int64_t m,
-                          const int32_t *__restrict__ src, const int32_t *__restrict__ row_ptr,
-                          int2 *__restrict__ in_tail, int32_t *__restrict__ in_slot) {
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m;
-       j += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t p = (int32_t)slots[j];
-    in_slot[j] = p;
-    in_tail[j] = make_int2(p + 1, row_ptr[src[p] + 1]);
+// Sorted by head vertex: in-degrees per run; the tail range of every in-edge.
+__global__ void k_in_fill(const uint64_t *__restrict__ heads, const uint32_t *__restrict__ slots,
+                          int64_t m, const int32_t *__restrict__ src,
+                          const int32_t *__restrict__ row_ptr, int2 *__restrict__ in_tail,
+                          int32_t *__restrict__ in_slot, int32_t *__restrict__ indeg) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t span = (m + stride - 1) / stride * stride;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < span; j += stride) {
+    const bool valid = j < m;
+    int32_t x = 0;
+    if (valid) {
+      const int32_t p = (int32_t)slots[j];
+      x = (int32_t)heads[j];
+      in_slot[j] = p;
+      in_tail[j] = make_int2(p + 1, row_ptr[src[p] + 1]);
+    }
+    wave_run_count(valid, x, indeg);
   }
 }
 
@@ -159,17 +178,17 @@ gc_status build_in_lists(int32_t n, int32_t m, int bits, CsrStore &c, Workspace 
   void *sscr = ws.take<char>(sort_scratch_bytes(m));
   void *cscr = ws.take<char>(scan_scratch_bytes(n));
   const int32_t *col = static_cast<const int32_t *>(c.col.ptr);
-  k_in_keys<<<gsz(m), BLK, 0, s>>>(col, m, ka, va, in_ptr);
+  k_in_keys<<<gsz(m), BLK, 0, s>>>(col, m, ka, va);
   GC_LAUNCH_CHECK();
   uint64_t *ks;
   uint32_t *vs;
   GC_TRY(radix_sort(ka, kb, va, vb, m, bits, sscr, s, &ks, &vs));
-  GC_TRY(exclusive_scan(in_ptr, in_ptr, n, cscr, s));
-  k_in_fill<<<gsz(m), BLK, 0, s>>>(vs, m, static_cast<const int32_t *>(c.src.ptr),
+  k_in_fill<<<gsz(m), BLK, 0, s>>>(ks, vs, m, static_cast<const int32_t *>(c.src.ptr),
                                    static_cast<const int32_t *>(c.row_ptr.ptr),
                                    static_cast<int2 *>(c.in_tail.ptr),
-                                   static_cast<int32_t *>(c.in_slot.ptr));
+                                   static_cast<int32_t *>(c.in_slot.ptr), in_ptr);
   GC_LAUNCH_CHECK();
+  GC_TRY(exclusive_scan(in_ptr, in_ptr, n, cscr, s));
   return GC_OK;
 }
 
@@ -182,6 +201,7 @@ static gc_status build_impl(const int32_t *d_src, const int32_t *d_dst, int64_t 
   const int shift = (flags & GC_INPUT_ONE_BASED) ? 1 : 0;
 
   GC_TRY(dalloc(g->rank, sizeof(int32_t) * ((size_t)n + 1)));
+  GC_TRY(dalloc(g->vid, sizeof(int32_t) * ((size_t)n + 1)));
   GC_TRY(dalloc(g->csr.row_ptr, sizeof(int32_t) * ((size_t)n + 1)));
 
   // ---- workspace for the build (released at the end) ----
@@ -245,7 +265,7 @@ static gc_status build_impl(const int32_t *d_src, const int32_t *d_dst, int64_t 
     GC_LAUNCH_CHECK();
     uint64_t *ks;
     GC_TRY(radix_sort(ka, kb, nullptr, nullptr, n, keybits, sscr, s, &ks, nullptr));
-    k_ranks<<<gsz(n), BLK, 0, s>>>(ks, n, bits, rank);
+    k_ranks<<<gsz(n), BLK, 0, s>>>(ks, n, bits, rank, static_cast<int32_t *>(g->vid.ptr));
     GC_LAUNCH_CHECK();
   }
 

@@ -148,4 +148,33 @@ GC_DEVICE_INLINE int32_t wave_inclusive_scan(int32_t v) {
   return v;
 }
 
+// Append `take` (per lane) to a global list with one atomic per wave: returns
+// this lane's slot (valid where take is true).  Works with any set of active
+// lanes: the ballot only sees active lanes.
+GC_DEVICE_INLINE int32_t wave_append(bool take, int32_t *counter) {
+  const uint64_t mask = __ballot(take);
+  if (mask == 0) return -1;
+  const int leader = __ffsll((long long)mask) - 1;
+  int32_t base = 0;
+  if ((int)__lane_id() == leader) base = atomicAdd(counter, (int32_t)__popcll(mask));
+  base = __shfl(base, leader, 64);
+  return base + (int32_t)__popcll(mask & lanemask_lt());
+}
+
+// counts[key] += number of lanes holding `key`, for keys sorted along the
+// wave (equal keys in consecutive lanes): one atomic per run of equal keys.
+// Every lane of the wave must call this; lanes with valid == false add
+// nothing.
+GC_DEVICE_INLINE void wave_run_count(bool valid, int32_t key, int32_t *counts) {
+  const int lane = (int)__lane_id();
+  const int32_t k = valid ? key : -1;
+  const int32_t prev = __shfl_up(k, 1, 64);
+  const uint64_t bounds = __ballot(lane == 0 || k != prev);
+  if (valid && (lane == 0 || k != prev)) {
+    const uint64_t after = lane == 63 ? 0ull : (bounds >> (lane + 1));
+    const int len = after ? __ffsll((long long)after) : 64 - lane;
+    atomicAdd(&counts[k], len);
+  }
+}
+
 }  // namespace gc

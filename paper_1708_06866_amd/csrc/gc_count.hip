@@ -28,6 +28,7 @@ constexpr int CBLK = 256;
 constexpr int CWAVES = CBLK / 64;
 constexpr int UNIT_CHUNK = 128;  // in-edges per work unit
 constexpr int NBINS = 5;
+constexpr int TC_UNROLL = 4;     // tail loads in flight per lane
 
 // Out-degree bounds of the bins (inclusive); the last bin is unbounded.
 __host__ __device__ constexpr int bin_limit_count(int b) {
@@ -127,10 +128,27 @@ gc_status build_units_support(const CsrView &c, UnitStore &u, Workspace &ws, hip
 // ----------------------------------------------------------------------------
 // Triangle count
 // ----------------------------------------------------------------------------
+// Where counts go: one total, or one counter per graph of a batch (the graph
+// of a unit is the graph of its middle vertex).
+struct CountOut {
+  unsigned long long *total = nullptr;
+  unsigned long long *per_graph = nullptr;
+  const int32_t *graph_of_rank = nullptr;
+};
+
+__device__ __forceinline__ void flush_unit(const CountOut &o, int32_t v, int32_t hits,
+                                           unsigned long long &total, int lane) {
+  const int32_t s = wave_sum_i32(hits);
+  if (o.per_graph) {
+    if (lane == 0 && s) atomicAdd(&o.per_graph[o.graph_of_rank[v]], (unsigned long long)s);
+  } else {
+    total += (unsigned)s;
+  }
+}
+
 template <int LOGH>
 __global__ __launch_bounds__(CBLK) void k_tc_hash(CsrView c, const int4 *__restrict__ units,
-                                                  int64_t nunits,
-                                                  unsigned long long *__restrict__ count) {
+                                                  int64_t nunits, CountOut out) {
   constexpr int H = 1 << LOGH;
   __shared__ int32_t tab[H];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -147,29 +165,38 @@ __global__ __launch_bounds__(CBLK) void k_tc_hash(CsrView c, const int4 *__restr
     }
     __syncthreads();
     int32_t hits = 0;
-    for (int32_t j = U.y + wave; j < U.z; j += CWAVES) {
-      const int2 t = c.in_tail[j];
-      for (int32_t p = t.x + lane; p < t.y; p += 64) {
-        const int32_t w = c.col[p];
-        uint32_t h = hslot(w, LOGH);
-        for (;;) {
-          const int32_t x = tab[h];
-          if (x == w) { ++hits; break; }
-          if (x < 0) break;
-          h = (h + 1) & (H - 1);
+    int32_t j = U.y + wave;
+    int2 t = j < U.z ? c.in_tail[j] : make_int2(0, 0);
+    for (; j < U.z; j += CWAVES) {
+      // prefetch the next in-edge's tail range while this one streams
+      const int2 tn = j + CWAVES < U.z ? c.in_tail[j + CWAVES] : make_int2(0, 0);
+      for (int32_t p = t.x + lane; p < t.y; p += 64 * TC_UNROLL) {
+        int32_t w[TC_UNROLL];
+#pragma unroll
+        for (int k = 0; k < TC_UNROLL; ++k) w[k] = p + 64 * k < t.y ? c.col[p + 64 * k] : -1;
+#pragma unroll
+        for (int k = 0; k < TC_UNROLL; ++k) {
+          if (w[k] < 0) continue;
+          uint32_t h = hslot(w[k], LOGH);
+          for (;;) {
+            const int32_t x = tab[h];
+            if (x == w[k]) { ++hits; break; }
+            if (x < 0) break;
+            h = (h + 1) & (H - 1);
+          }
         }
       }
+      t = tn;
     }
-    total += (unsigned)wave_sum_i32(hits);
+    flush_unit(out, U.x, hits, total, lane);
     __syncthreads();
   }
-  if (lane == 0 && total) atomicAdd(count, total);
+  if (!out.per_graph && lane == 0 && total) atomicAdd(out.total, total);
 }
 
 // Out-lists too long for LDS: binary search in the sorted row in global memory.
 __global__ __launch_bounds__(CBLK) void k_tc_search(CsrView c, const int4 *__restrict__ units,
-                                                    int64_t nunits,
-                                                    unsigned long long *__restrict__ count) {
+                                                    int64_t nunits, CountOut out) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   unsigned long long total = 0;
   for (int64_t ui = blockIdx.x; ui < nunits; ui += gridDim.x) {
@@ -188,9 +215,9 @@ __global__ __launch_bounds__(CBLK) void k_tc_search(CsrView c, const int4 *__res
         hits += (lo < re && c.col[lo] == w) ? 1 : 0;
       }
     }
-    total += (unsigned)wave_sum_i32(hits);
+    flush_unit(out, U.x, hits, total, lane);
   }
-  if (lane == 0 && total) atomicAdd(count, total);
+  if (!out.per_graph && lane == 0 && total) atomicAdd(out.total, total);
 }
 
 static unsigned unit_grid(int64_t nunits, int per_cu) {
@@ -199,23 +226,68 @@ static unsigned unit_grid(int64_t nunits, int per_cu) {
   return (unsigned)(g < 1 ? 1 : g);
 }
 
-gc_status count_triangles(const CsrView &c, const UnitStore &u, unsigned long long *d_count,
-                          hipStream_t s) {
+// Strategies per bin: 0 = LDS hash at the bin's table size (load <= 1/2),
+// 1 = LDS hash with a table twice as large (load <= 1/4), 2 = binary search
+// in HBM.  The last bin only admits 2.
+bool count_strategy_valid(int bin, int strategy) {
+  if (strategy == 2) return true;
+  return bin < NBINS - 1 && (strategy == 0 || strategy == 1);
+}
+
+static gc_status launch_count_bin(const CsrView &c, const int4 *ub, int64_t nu, int b,
+                                  int strategy, const CountOut &o, hipStream_t s) {
+  if (strategy == 2 || b == NBINS - 1) {
+    k_tc_search<<<unit_grid(nu, 8), CBLK, 0, s>>>(c, ub, nu, o);
+  } else {
+    const int logh = (b == 0 ? 6 : b == 1 ? 9 : b == 2 ? 12 : 14) + (strategy == 1 ? 1 : 0);
+    switch (logh) {
+      case 6: k_tc_hash<6><<<unit_grid(nu, 16), CBLK, 0, s>>>(c, ub, nu, o); break;
+      case 7: k_tc_hash<7><<<unit_grid(nu, 16), CBLK, 0, s>>>(c, ub, nu, o); break;
+      case 9: k_tc_hash<9><<<unit_grid(nu, 16), CBLK, 0, s>>>(c, ub, nu, o); break;
+      case 10: k_tc_hash<10><<<unit_grid(nu, 16), CBLK, 0, s>>>(c, ub, nu, o); break;
+      case 12: k_tc_hash<12><<<unit_grid(nu, 8), CBLK, 0, s>>>(c, ub, nu, o); break;
+      case 13: k_tc_hash<13><<<unit_grid(nu, 4), CBLK, 0, s>>>(c, ub, nu, o); break;
+      case 14: k_tc_hash<14><<<unit_grid(nu, 4), CBLK, 0, s>>>(c, ub, nu, o); break;
+      default: k_tc_hash<15><<<unit_grid(nu, 2), CBLK, 0, s>>>(c, ub, nu, o); break;
+    }
+  }
+  GC_LAUNCH_CHECK();
+  return GC_OK;
+}
+
+gc_status count_triangles_ex(const CsrView &c, const UnitStore &u, unsigned long long *d_total,
+                             unsigned long long *d_per_graph, const int32_t *graph_of_rank,
+                             const int *strategy, hipStream_t s) {
   const int4 *units = static_cast<const int4 *>(u.units.ptr);
+  CountOut o;
+  o.total = d_total;
+  o.per_graph = d_per_graph;
+  o.graph_of_rank = graph_of_rank;
   for (int b = 0; b < NBINS; ++b) {
     const int64_t nu = u.bin_count[b];
     if (nu == 0) continue;
-    const int4 *ub = units + u.bin_begin[b];
-    switch (b) {
-      case 0: k_tc_hash<6><<<unit_grid(nu, 16), CBLK, 0, s>>>(c, ub, nu, d_count); break;
-      case 1: k_tc_hash<9><<<unit_grid(nu, 16), CBLK, 0, s>>>(c, ub, nu, d_count); break;
-      case 2: k_tc_hash<12><<<unit_grid(nu, 8), CBLK, 0, s>>>(c, ub, nu, d_count); break;
-      case 3: k_tc_hash<14><<<unit_grid(nu, 4), CBLK, 0, s>>>(c, ub, nu, d_count); break;
-      default: k_tc_search<<<unit_grid(nu, 8), CBLK, 0, s>>>(c, ub, nu, d_count); break;
-    }
-    GC_LAUNCH_CHECK();
+    const int st = strategy ? strategy[b] : (b == NBINS - 1 ? 2 : 0);
+    GC_TRY(launch_count_bin(c, units + u.bin_begin[b], nu, b, st, o, s));
   }
   return GC_OK;
+}
+
+gc_status count_bin(const CsrView &c, const UnitStore &u, int bin, int strategy,
+                    unsigned long long *d_total, unsigned long long *d_per_graph,
+                    const int32_t *graph_of_rank, hipStream_t s) {
+  const int64_t nu = u.bin_count[bin];
+  if (nu == 0) return GC_OK;
+  CountOut o;
+  o.total = d_total;
+  o.per_graph = d_per_graph;
+  o.graph_of_rank = graph_of_rank;
+  return launch_count_bin(c, static_cast<const int4 *>(u.units.ptr) + u.bin_begin[bin], nu, bin,
+                          strategy, o, s);
+}
+
+gc_status count_triangles(const CsrView &c, const UnitStore &u, unsigned long long *d_count,
+                          hipStream_t s) {
+  return count_triangles_ex(c, u, d_count, nullptr, nullptr, nullptr, s);
 }
 
 // ----------------------------------------------------------------------------
@@ -244,19 +316,25 @@ __global__ __launch_bounds__(CBLK) void k_sup_hash(CsrView c, const int4 *__rest
     for (int32_t j = U.y + wave; j < U.z; j += CWAVES) {
       const int2 t = c.in_tail[j];
       int32_t mine = 0;
-      for (int32_t p = t.x + lane; p < t.y; p += 64) {
-        const int32_t w = c.col[p];
-        uint32_t h = hslot(w, LOGH);
-        for (;;) {
-          const int32_t x = tab[h];
-          if (x == w) {
-            ++mine;
-            atomicAdd(&tcnt[h], 1);   // edge b -> c
-            atomicAdd(&sup[p], 1);    // edge a -> c
-            break;
+      for (int32_t p = t.x + lane; p < t.y; p += 64 * TC_UNROLL) {
+        int32_t w[TC_UNROLL];
+#pragma unroll
+        for (int k = 0; k < TC_UNROLL; ++k) w[k] = p + 64 * k < t.y ? c.col[p + 64 * k] : -1;
+#pragma unroll
+        for (int k = 0; k < TC_UNROLL; ++k) {
+          if (w[k] < 0) continue;
+          uint32_t h = hslot(w[k], LOGH);
+          for (;;) {
+            const int32_t x = tab[h];
+            if (x == w[k]) {
+              ++mine;
+              atomicAdd(&tcnt[h], 1);             // edge b -> c
+              atomicAdd(&sup[p + 64 * k], 1);     // edge a -> c
+              break;
+            }
+            if (x < 0) break;
+            h = (h + 1) & (H - 1);
           }
-          if (x < 0) break;
-          h = (h + 1) & (H - 1);
         }
       }
       const int32_t tot = wave_sum_i32(mine);

@@ -65,6 +65,7 @@ struct gc_graph {
   int64_t m = 0;
   int bits = 1;  // bits per vertex id: 2^bits >= n
   gc::DeviceBuffer u, v, rank;
+  gc::DeviceBuffer vid;         // vid[r] = original id of the vertex of rank r
   gc::CsrStore csr;
   gc::UnitStore units;      // count-kernel work units of the base CSR
   bool units_ready = false;
@@ -75,12 +76,12 @@ struct gc_graph {
   gc::UnitStore work_units;
   gc::DeviceBuffer t_sup, t_flag, t_pos, t_misc;  // k-truss round state
   size_t device_bytes() const {
-    return u.bytes + v.bytes + rank.bytes + csr.bytes() + units.units.bytes +
+    return u.bytes + v.bytes + rank.bytes + vid.bytes + csr.bytes() + units.units.bytes +
            units_sup.units.bytes + ws.buf.bytes + work[0].bytes() + work[1].bytes() +
            work_units.units.bytes + t_sup.bytes + t_flag.bytes + t_pos.bytes + t_misc.bytes;
   }
   void release() {
-    gc::dfree(u); gc::dfree(v); gc::dfree(rank);
+    gc::dfree(u); gc::dfree(v); gc::dfree(rank); gc::dfree(vid);
     csr.release(); work[0].release(); work[1].release();
     gc::dfree(units.units); gc::dfree(units_sup.units); gc::dfree(work_units.units);
     gc::dfree(t_sup); gc::dfree(t_flag); gc::dfree(t_pos); gc::dfree(t_misc);
@@ -99,6 +100,17 @@ gc_status build_units(const CsrView &c, UnitStore &u, Workspace &ws, hipStream_t
 gc_status build_units_support(const CsrView &c, UnitStore &u, Workspace &ws, hipStream_t s);
 gc_status count_triangles(const CsrView &c, const UnitStore &u, unsigned long long *d_count,
                           hipStream_t s);
+constexpr int kCountBins = 5;
+constexpr int kCountStrategies = 3;  // 0 hash (load <= 1/2), 1 hash (load <= 1/4), 2 search
+bool count_strategy_valid(int bin, int strategy);
+// Count with a chosen strategy per bin (strategy may be null = defaults); per
+// graph counts if d_per_graph != null (graph_of_rank maps a rank to its graph).
+gc_status count_triangles_ex(const CsrView &c, const UnitStore &u, unsigned long long *d_total,
+                             unsigned long long *d_per_graph, const int32_t *graph_of_rank,
+                             const int *strategy, hipStream_t s);
+gc_status count_bin(const CsrView &c, const UnitStore &u, int bin, int strategy,
+                    unsigned long long *d_total, unsigned long long *d_per_graph,
+                    const int32_t *graph_of_rank, hipStream_t s);
 gc_status slot_support(const CsrView &c, const UnitStore &u, int32_t *d_sup, hipStream_t s);
 // (gc_peel.hip) truss numbers by peeling with incremental support updates;
 // tau must hold m entries.

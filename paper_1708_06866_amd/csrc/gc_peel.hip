@@ -44,23 +44,28 @@ __device__ __forceinline__ int32_t find_col(const int32_t *__restrict__ col, int
   return (lo < end && col[lo] == key) ? lo : -1;
 }
 
-__device__ __forceinline__ void drop_one(int32_t q, int32_t thr, int32_t *__restrict__ sup,
-                                         int32_t *__restrict__ next,
-                                         int32_t *__restrict__ next_count) {
-  const int32_t old = atomicSub(&sup[q], 1);
-  if (old == thr) next[atomicAdd(next_count, 1)] = q;
-}
-
-// Triangle {p, q1, q2} seen from frontier edge p.
-__device__ __forceinline__ void destroy(int32_t p, int32_t q1, int32_t q2, int32_t thr,
-                                        const uint8_t *__restrict__ state,
+// Triangle {p, q1, q2} seen from frontier edge p (q2 < 0: no triangle).  Every
+// active lane of the wave calls this together, so the next-frontier appends
+// are aggregated per wave.
+__device__ __forceinline__ void destroy(bool found, int32_t p, int32_t q1, int32_t q2,
+                                        int32_t thr, const uint8_t *__restrict__ state,
                                         int32_t *__restrict__ sup, int32_t *__restrict__ next,
                                         int32_t *__restrict__ next_count) {
-  const uint8_t s1 = state[q1], s2 = state[q2];
-  if (s1 == EDGE_DEAD || s2 == EDGE_DEAD) return;  // destroyed in an earlier round
-  if ((s1 == EDGE_FRONT && q1 < p) || (s2 == EDGE_FRONT && q2 < p)) return;  // not ours
-  if (s1 == EDGE_ALIVE) drop_one(q1, thr, sup, next, next_count);
-  if (s2 == EDGE_ALIVE) drop_one(q2, thr, sup, next, next_count);
+  bool t1 = false, t2 = false;
+  if (found) {
+    const uint8_t s1 = state[q1], s2 = state[q2];
+    // skip if destroyed in an earlier round, or owned by a smaller frontier edge
+    const bool ours = s1 != EDGE_DEAD && s2 != EDGE_DEAD &&
+                      !(s1 == EDGE_FRONT && q1 < p) && !(s2 == EDGE_FRONT && q2 < p);
+    if (ours) {
+      if (s1 == EDGE_ALIVE) t1 = atomicSub(&sup[q1], 1) == thr;
+      if (s2 == EDGE_ALIVE) t2 = atomicSub(&sup[q2], 1) == thr;
+    }
+  }
+  int32_t at = wave_append(t1, next_count);
+  if (t1) next[at] = q1;
+  at = wave_append(t2, next_count);
+  if (t2) next[at] = q2;
 }
 
 __global__ __launch_bounds__(PBLK) void k_peel(CsrView c, const int32_t *__restrict__ front,
@@ -79,20 +84,24 @@ __global__ __launch_bounds__(PBLK) void k_peel(CsrView c, const int32_t *__restr
     // third vertex from the out-row of a
     const int32_t ra1 = c.row_ptr[a + 1];
     for (int32_t i = c.row_ptr[a] + lane; i < ra1; i += 64) {
-      if (i == p || state[i] == EDGE_DEAD) continue;
-      const int32_t x = c.col[i];
-      const int32_t q2 = x > b ? find_col(c.col, rb0, rb1, x)
-                               : find_col(c.col, c.row_ptr[x], c.row_ptr[x + 1], b);
-      if (q2 >= 0) destroy(p, i, q2, thr, state, sup, next, next_count);
+      int32_t q2 = -1;
+      if (i != p && state[i] != EDGE_DEAD) {
+        const int32_t x = c.col[i];
+        q2 = x > b ? find_col(c.col, rb0, rb1, x)
+                   : find_col(c.col, c.row_ptr[x], c.row_ptr[x + 1], b);
+      }
+      destroy(q2 >= 0, p, i, q2, thr, state, sup, next, next_count);
     }
     // third vertex below a: from the in-list of a
     const int32_t ia1 = c.in_ptr[a + 1];
     for (int32_t j = c.in_ptr[a] + lane; j < ia1; j += 64) {
       const int32_t q1 = c.in_slot[j];
-      if (state[q1] == EDGE_DEAD) continue;
-      const int32_t x = c.src[q1];
-      const int32_t q2 = find_col(c.col, c.row_ptr[x], c.row_ptr[x + 1], b);
-      if (q2 >= 0) destroy(p, q1, q2, thr, state, sup, next, next_count);
+      int32_t q2 = -1;
+      if (state[q1] != EDGE_DEAD) {
+        const int32_t x = c.src[q1];
+        q2 = find_col(c.col, c.row_ptr[x], c.row_ptr[x + 1], b);
+      }
+      destroy(q2 >= 0, p, q1, q2, thr, state, sup, next, next_count);
     }
   }
 }
@@ -140,7 +149,13 @@ __global__ void k_compact_list(const int32_t *__restrict__ list, int32_t L,
     }
   }
   for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
-  if ((threadIdx.x & 63) == 0 && v != 0x7fffffff) atomicMin(dmin, v);
+  __shared__ int32_t wmin[4];
+  if ((threadIdx.x & 63) == 0) wmin[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    v = min(min(wmin[0], wmin[1]), min(wmin[2], wmin[3]));
+    if (v != 0x7fffffff) atomicMin(dmin, v);
+  }
 }
 
 __global__ void k_collect(const int32_t *__restrict__ list, int32_t L, int32_t thr,
@@ -149,9 +164,11 @@ __global__ void k_collect(const int32_t *__restrict__ list, int32_t L, int32_t t
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < L;
        i += (int64_t)gridDim.x * blockDim.x) {
     const int32_t p = list[i];
-    if (sup[p] < thr) {
+    const bool take = sup[p] < thr;
+    const int32_t at = wave_append(take, count);
+    if (take) {
       state[p] = EDGE_FRONT;
-      front[atomicAdd(count, 1)] = p;
+      front[at] = p;
     }
   }
 }
@@ -311,7 +328,8 @@ gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStre
     GC_TRY(g->ws.reserve(scan_scratch_bytes((int64_t)L + 1)));
     GC_TRY(exclusive_scan(flag, pos, L, g->ws.take<char>(scan_scratch_bytes((int64_t)L + 1)), s));
     k_set_i32<<<1, 64, 0, s>>>(misc, 0, 0x7fffffff);
-    k_compact_list<<<gsz(L), 256, 0, s>>>(list, L, flag, pos, sup, list2, misc + 1);
+    k_compact_list<<<grid_for(L, 256, 2048), 256, 0, s>>>(list, L, flag, pos, sup, list2,
+                                                          misc + 1);
     GC_LAUNCH_CHECK();
     int32_t h[2];
     GC_HIP(hipMemcpyAsync(&h[0], pos + L, sizeof(int32_t), hipMemcpyDeviceToHost, s));

@@ -200,7 +200,7 @@ static gc_status decomposition_impl(gc_graph *g, int32_t *truss, int32_t *h_kmax
       // no removal at level k: every remaining edge has support >= min, so
       // levels k .. min+2 keep them all; continue at min + 3
       k_fill_i32<<<1, 64, 0, s>>>(dmin, 1, 0x7fffffff);
-      k_min_i32<<<gsz(c.m), 256, 0, s>>>(sup, c.m, dmin);
+      k_min_i32<<<grid_for(c.m, 256, 2048), 256, 0, s>>>(sup, c.m, dmin);
       int32_t hmin = 0;
       if (hipMemcpyAsync(&hmin, dmin, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
           hipStreamSynchronize(s) != hipSuccess) {
