@@ -95,6 +95,174 @@ def cpu_baseline(scale: int, ef: int, seed: int) -> dict:
             "seconds": round(dt, 2)}
 
 
+def batch_workload(n_graphs: int, seed: int = 1000, max_scale: int = 16):
+    """C4-style mix: half R-MAT (scale uniform 8..max_scale, i.e. vertex
+    counts log-uniform; edge factor uniform 8..32), half random geometric
+    graphs on the torus (n = 2^10..2^14 log-uniform, mean degree 20), shuffled;
+    graph i uses seed + i."""
+    import graphgen as gg
+    rng = np.random.default_rng(seed)
+    kinds = np.array([0] * (n_graphs // 2) + [1] * (n_graphs - n_graphs // 2))
+    rng.shuffle(kinds)
+    graphs = []
+    for i, kd in enumerate(kinds):
+        if kd == 0:
+            sc = int(rng.integers(8, max_scale + 1))
+            ef = int(rng.integers(8, 33))
+            graphs.append(gg.rmat(sc, ef, seed=seed + i))
+        else:
+            n = 1 << int(rng.integers(10, 15))
+            graphs.append(gg.rgg(n, 20.0, seed=seed + i))
+    return graphs
+
+
+def bench_batch(gc, torch, dev, n_graphs: int, max_scale: int) -> dict:
+    """Batched path vs one graph per call on the same GPU, exact agreement:
+    per-graph triangle count + 4-truss edge count."""
+    t = time.perf_counter()
+    graphs = batch_workload(n_graphs, max_scale=max_scale)
+    log("batch: generated %d graphs in %.1fs" % (len(graphs), time.perf_counter() - t))
+    srcs = [torch.from_numpy(g[0]) for g in graphs]
+    dsts = [torch.from_numpy(g[1]) for g in graphs]
+    off = np.zeros(len(graphs) + 1, dtype=np.int64)
+    off[1:] = np.cumsum([len(g[0]) for g in graphs])
+    nv = [g[2] for g in graphs]
+    d_src = torch.cat(srcs).to(dev)
+    d_dst = torch.cat(dsts).to(dev)
+    per_src = [x.to(dev) for x in srcs]
+    per_dst = [x.to(dev) for x in dsts]
+    torch.cuda.synchronize()
+
+    def run_batch():
+        b = gc.gc_batch_build(d_src, d_dst, off, nv)
+        T = b.triangle_count()
+        _, mk = b.ktruss(4)
+        torch.cuda.synchronize()
+        return b, T.cpu().numpy(), mk.cpu().numpy()
+
+    b, _, _ = run_batch()          # warm up (code objects, allocator)
+    st, _ = b.autotune()
+    b.free()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b, T_b, mk_b = run_batch()
+    t_batch = time.perf_counter() - t0
+    edges_total = int(b.edge_offsets[-1])
+    b.free()
+
+    # one graph per call, same GPU, same stream
+    T_c = np.zeros(len(graphs), np.int64)
+    mk_c = np.zeros(len(graphs), np.int64)
+    for i in range(min(8, len(graphs))):   # warm up
+        g = gc.gc_build_csr(per_src[i], per_dst[i], nv[i])
+        g.triangle_count()
+        g.free()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(len(graphs)):
+        g = gc.gc_build_csr(per_src[i], per_dst[i], nv[i])
+        T_c[i] = g.triangle_count()
+        mk_c[i] = g.ktruss(4)[1]
+        g.free()
+    torch.cuda.synchronize()
+    t_call = time.perf_counter() - t0
+    assert np.array_equal(T_b, T_c) and np.array_equal(mk_b, mk_c), "batched != per-call"
+    return {"graphs": len(graphs), "edges": edges_total, "raw_pairs": int(off[-1]),
+            "batched_s": round(t_batch, 4), "per_call_s": round(t_call, 4),
+            "batched_edges_per_s": edges_total / t_batch, "per_call_edges_per_s": edges_total / t_call,
+            "speedup": t_call / t_batch, "autotuned_strategy": st.tolist(),
+            "exact_agreement": True,
+            "workload": "half R-MAT (scale 8..%d, ef 8..32), half torus RGG (n 2^10..2^14, "
+                        "degree 20); per graph: triangle count + 4-truss" % max_scale}
+
+
+def serve_pool(n_graphs: int, seed: int = 5000, big_max: int = 18):
+    """Serving pool: R-MAT ef 16, scale uniform 10..14 with p = 0.9, else
+    uniform 15..big_max."""
+    import graphgen as gg
+    rng = np.random.default_rng(seed)
+    out = []
+    for j in range(n_graphs):
+        sc = int(rng.integers(10, 15)) if rng.random() < 0.9 else int(rng.integers(15, big_max + 1))
+        out.append(gg.rmat(sc, 16, seed=seed + j))
+    return out
+
+
+def bench_serve(gc, n_graphs: int, n_requests: int, big_max: int, budget: int) -> dict:
+    """Poisson arrivals at 0.7 x the one-request-at-a-time capacity; the same
+    trace served with continuous batching and one request at a time.  Half of
+    the requests count triangles, half ask for the 4-truss size."""
+    import threading
+    pool = serve_pool(n_graphs, big_max=big_max)
+    rng = np.random.default_rng(7)
+    reqs = [(int(rng.integers(0, n_graphs)), int(rng.random() < 0.5)) for _ in range(n_requests)]
+
+    def make_server(mode):
+        srv = gc.Server(budget, mode=mode)
+        for s_, d_, n_ in pool:
+            srv.add_graph(s_, d_, n_)
+        # first touch of every graph (builds) outside the measurement
+        for t in [srv.submit(i) for i in range(n_graphs)]:
+            srv.wait(t)
+        return srv
+
+    def run(srv, trace_gaps):
+        res = [None] * len(reqs)
+        tickets = [None] * len(reqs)
+        def submitter():
+            t_next = time.monotonic()
+            for i, (g, kind) in enumerate(reqs):
+                if trace_gaps is not None:
+                    t_next += trace_gaps[i]
+                    dt = t_next - time.monotonic()
+                    if dt > 0:
+                        time.sleep(dt)
+                tickets[i] = srv.submit(g, kind, 4 if kind else 0)
+        th = threading.Thread(target=submitter)
+        t0 = time.monotonic()
+        th.start()
+        th.join()
+        for i in range(len(reqs)):
+            res[i] = srv.wait(tickets[i])
+        wall = time.monotonic() - t0
+        lat = np.array([r["t_done"] - r["t_submit"] for r in res])
+        edges = sum(r["edges"] for r in res)
+        return res, wall, lat, edges
+
+    # capacity of the one-at-a-time path: the whole trace submitted at once
+    srv1 = make_server(1)
+    res_sat1, wall_sat1, _, edges = run(srv1, None)
+    cap = len(reqs) / wall_sat1
+    lam = 0.7 * cap
+    gaps = np.random.default_rng(8).exponential(1.0 / lam, len(reqs))
+    res_p1, wall_p1, lat_p1, _ = run(srv1, gaps)
+    srv1.close()
+    srv0 = make_server(0)
+    res_sat0, wall_sat0, _, _ = run(srv0, None)
+    res_p0, wall_p0, lat_p0, _ = run(srv0, gaps)
+    stats0 = srv0.stats()
+    srv0.close()
+    vals = [r["value"] for r in res_sat1]
+    for other in (res_p1, res_sat0, res_p0):
+        assert [r["value"] for r in other] == vals, "results differ between modes"
+    pct = lambda a, q: float(np.percentile(a, q) * 1000.0)
+    return {
+        "requests": len(reqs), "graphs": n_graphs, "offered_load_req_per_s": lam,
+        "per_call": {"p50_ms": pct(lat_p1, 50), "p99_ms": pct(lat_p1, 99),
+                     "edges_per_s_at_load": edges / wall_p1,
+                     "saturated_edges_per_s": edges / wall_sat1,
+                     "saturated_req_per_s": len(reqs) / wall_sat1},
+        "continuous_batching": {"p50_ms": pct(lat_p0, 50), "p99_ms": pct(lat_p0, 99),
+                                "edges_per_s_at_load": edges / wall_p0,
+                                "saturated_edges_per_s": edges / wall_sat0,
+                                "saturated_req_per_s": len(reqs) / wall_sat0,
+                                "max_batch": stats0["max_batch"], "batches": stats0["batches"]},
+        "exact_agreement": True,
+        "workload": "R-MAT ef 16 pool, scale 10..14 (p=0.9) / 15..%d; 50%% triangle count, "
+                    "50%% 4-truss size; Poisson arrivals at 0.7 x per-call capacity" % big_max,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,6 +276,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-decomposition", action="store_true",
                     help="step = build + count only")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the per-bin strategy autotuner (run before the timed steps)")
+    ap.add_argument("--batch-graphs", type=int, default=512,
+                    help="graphs in the batched-path comparison (0: skip)")
+    ap.add_argument("--batch-max-scale", type=int, default=14)
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="requests in the serving comparison (0: skip)")
+    ap.add_argument("--serve-graphs", type=int, default=128)
+    ap.add_argument("--serve-big-max", type=int, default=17)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one elementwise int32 kernel over 1 GiB (reads 1 GiB, "
                          "writes 1 GiB) so HBM counters can be scaled against known bytes")
@@ -145,6 +322,20 @@ def main():
 
     stream = torch.cuda.current_stream()
     tau_buf = None
+    record_stats = {}
+
+    tuned = None
+    if not args.no_autotune:
+        # the autotuner times every count strategy per degree bin on this graph
+        # and writes its choice to a cache file that later builds read
+        import tempfile
+        os.environ.setdefault("GC_AUTOTUNE_CACHE",
+                              os.path.join(tempfile.gettempdir(), "gc_autotune_%d.txt" % os.getpid()))
+        g = gc.gc_build_csr(d_src, d_dst, n)
+        st, ms = g.autotune()
+        g.free()
+        tuned = {"strategy": st.tolist(), "ms": [[round(float(x), 3) for x in row] for row in ms]}
+        log("autotune: strategy per bin %s; ms per bin x strategy %s" % (tuned["strategy"], tuned["ms"]))
 
     def step(record):
         nonlocal tau_buf
@@ -160,6 +351,8 @@ def main():
                 tau_buf = torch.empty(max(g.m, 1), dtype=torch.int32, device=dev)
             _, kmax = g.truss_decomposition(out=tau_buf)
         ev[3].record(stream)
+        if kmax is not None:
+            record_stats.update(g.truss_stats())
         m = g.m
         record.append((ev, T, kmax, m))
         return g
@@ -225,6 +418,8 @@ def main():
             "triangles": int(T), "kmax": kmax,
         },
         "phases_ms": {"build": build_ms, "triangle_count": tc_ms, "decomposition": dec_ms},
+        "autotune": tuned,
+        "decomposition_stats": record_stats or None,
         "tc_edges_per_s": m / (tc_ms / 1000.0),
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -234,6 +429,15 @@ def main():
             "survey_model_bytes": ab["B_model_min"],
         },
     }
+    if args.batch_graphs > 0:
+        log("batched path: %d graphs ..." % args.batch_graphs)
+        out["batch"] = bench_batch(gc, torch, dev, args.batch_graphs, args.batch_max_scale)
+        log("batch: %s" % json.dumps(out["batch"]))
+    if args.serve_requests > 0:
+        log("serving: %d requests on %d graphs ..." % (args.serve_requests, args.serve_graphs))
+        out["serve"] = bench_serve(gc, args.serve_graphs, args.serve_requests,
+                                   args.serve_big_max, 64 << 30)
+        log("serve: %s" % json.dumps(out["serve"]))
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on R-MAT scale %d ..." % args.cpu_scale)
         out["cpu_baseline"] = cpu_baseline(args.cpu_scale, args.ef, args.seed)

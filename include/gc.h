@@ -125,12 +125,40 @@ gc_status gc_edge_support(gc_graph *g, int32_t *d_support, int64_t cap,
 gc_status gc_ktruss(gc_graph *g, int32_t k, uint8_t *d_in_truss, int64_t cap,
                     gc_stream stream, int64_t *h_m_k);
 
+/* Count strategies per degree bin (the 5 bins split middle vertices by
+ * out-degree: <= 32, <= 256, <= 2048, <= 8192, larger):
+ *   0 linear-probing LDS hash table, load <= 1/2
+ *   1 linear-probing LDS hash table, load <= 1/4
+ *   2 binary search in the sorted row in HBM (the only one for the last bin)
+ *   3 bucketed LDS hash table (4 slots per 16-byte bucket), load <= 1/2
+ *   4 bucketed LDS hash table, load <= 1/4
+ * Results never depend on the strategy.  A new handle takes them from the
+ * file named by the environment variable GC_AUTOTUNE_CACHE if it exists
+ * (lines "<arch> <bin> <strategy>"), else {0, 0, 0, 0, 2}. */
+
+/* Autotuner: time every admissible strategy of every bin that has work on
+ * this graph (HIP events, first run discarded), keep the fastest per bin and,
+ * if GC_AUTOTUNE_CACHE is set, write the choices there.  h_strategy[5] and
+ * h_ms[5*5] (mean ms per bin and strategy, -1 where not run) may be NULL.
+ * Synchronises `stream`. */
+gc_status gc_graph_autotune(gc_graph *g, gc_stream stream, int32_t *h_strategy,
+                            float *h_ms);
+
+/* Set the 5 per-bin strategies (GC_EINVAL if one is not admissible). */
+gc_status gc_graph_set_strategy(gc_graph *g, const int32_t *h_strategy);
+
 /* Truss decomposition (Sec. III-B, last paragraph): d_truss[e] = the largest
  * k such that canonical edge e belongs to the k-truss (>= 2), and *h_kmax the
  * largest k with a non-empty k-truss (0 for an empty graph, 2 if there are
  * edges but no triangle).  Either output may be NULL.  Synchronises `stream`. */
 gc_status gc_truss_decomposition(gc_graph *g, int32_t *d_truss, int64_t cap,
                                  gc_stream stream, int32_t *h_kmax);
+
+/* Counters of the last gc_truss_decomposition on this handle (first `cap`
+ * of 37, host): [0] levels that removed edges, [1] rounds, [2] edges removed
+ * over all rounds (= m), [3] largest round, [4] compactions of the edge list,
+ * [5 + i] rounds whose removal count r has floor(log2 r) = i. */
+gc_status gc_graph_truss_stats(const gc_graph *g, int64_t *h_stats, int32_t cap);
 
 /* ------------------------------------------------------------------------ */
 /* Batches: many independent graphs counted in one launch per degree bin.    */
@@ -179,22 +207,85 @@ gc_status gc_batch_edge_support(gc_batch *b, int32_t *d_support, int64_t cap,
 gc_status gc_batch_ktruss(gc_batch *b, int32_t k, uint8_t *d_mask, int64_t cap,
                           int64_t *d_mk, gc_stream stream);
 
-/* Autotuner: for each degree bin that has work, time every admissible count
- * strategy on this batch (0: LDS hash, load <= 1/2; 1: LDS hash, load <= 1/4;
- * 2: binary search in HBM) and keep the fastest.  h_strategy[5] (host, may
- * be NULL) receives the choices, h_ms[5*3] (may be NULL) the mean times in ms
- * (-1 where not run).  If the environment variable GC_AUTOTUNE_CACHE names a
- * file, choices are written there and read back by later gc_batch_build calls
- * (lines "<arch> <bin> <strategy>").  Results never depend on the choice. */
+/* Autotuner of a batch, as gc_graph_autotune (strategies listed there):
+ * times every admissible count strategy per degree bin on the whole batch,
+ * keeps the fastest, writes GC_AUTOTUNE_CACHE if set.  h_strategy[5] and
+ * h_ms[5*5] may be NULL.  Results never depend on the choice. */
 gc_status gc_batch_autotune(gc_batch *b, gc_stream stream, int32_t *h_strategy,
                             float *h_ms);
 
 /* Force the count strategy of each of the 5 bins (GC_EINVAL if a strategy is
- * not admissible for its bin; the last bin admits only 2). */
+ * not admissible for its bin; the last bin admits only 2).  Drops the
+ * captured HIP graph. */
 gc_status gc_batch_set_strategy(gc_batch *b, const int32_t *h_strategy);
 
 /* Release a batch and its union graph (NULL is a no-op). */
 void gc_batch_free(gc_batch *b);
+
+/* ------------------------------------------------------------------------ */
+/* Serving: queries on registered graphs with continuous batching.          */
+/* ------------------------------------------------------------------------ */
+typedef struct gc_server gc_server;
+
+#define GC_PENDING 1 /* gc_server_poll: the request has not completed yet */
+
+/* A query on a registered graph: kind 0 = triangle count (Sec. III-A),
+ * kind 1 = number of edges in the k-truss (Sec. III-B), k >= 2. */
+typedef struct {
+  int32_t graph_id;
+  int32_t kind;
+  int32_t k;
+  int32_t reserved;
+} gc_request;
+
+/* Outcome of a query: status (GC_OK or an error), the value (triangles or
+ * k-truss edges), the graph's edge count m, and CLOCK_MONOTONIC timestamps in
+ * seconds: submission, start on the device, completion. */
+typedef struct {
+  int32_t status;
+  int32_t kind;
+  int64_t value;
+  int64_t edges;
+  double t_submit;
+  double t_start;
+  double t_done;
+} gc_result;
+
+/* Start a server on the current device with an HBM budget in bytes.  A
+ * scheduler thread keeps built graphs resident (evicting idle ones, least
+ * recently used first, when the budget needs room), admits a request only
+ * when the budget can hold its graph's build, and runs every triangle-count
+ * request whose graph is resident in one batched launch per degree bin,
+ * forming the next batch from whatever arrived while the previous one ran.
+ * k-truss queries run on a worker thread with their own stream. */
+gc_status gc_server_create(int64_t budget_bytes, gc_server **out);
+
+/* 0 = continuous batching (default); 1 = one request at a time in arrival
+ * order with the same cache (the per-call comparison). */
+gc_status gc_server_set_mode(gc_server *s, int32_t mode);
+
+/* Register a graph: raw pairs in host memory (copied), ids in
+ * [0, n_vertices).  GC_ENOMEM if its build can never fit the budget. */
+gc_status gc_server_add_graph(gc_server *s, const int32_t *h_src,
+                              const int32_t *h_dst, int64_t n_pairs,
+                              int32_t n_vertices, int32_t *graph_id);
+
+/* Queue a query; *ticket identifies it.  Thread-safe. */
+gc_status gc_server_submit(gc_server *s, const gc_request *req, int64_t *ticket);
+
+/* GC_OK with *out filled (the ticket is then released), or GC_PENDING. */
+gc_status gc_server_poll(gc_server *s, int64_t ticket, gc_result *out);
+
+/* Block until the query completes, then as gc_server_poll. */
+gc_status gc_server_wait(gc_server *s, int64_t ticket, gc_result *out);
+
+/* h_stats[10]: completed, batches, largest batch, builds, evictions, bytes
+ * charged now, peak bytes charged, admissions deferred for memory, resident
+ * graphs, budget. */
+gc_status gc_server_stats(gc_server *s, int64_t *h_stats);
+
+/* Stop the threads and release every resident graph (NULL is a no-op). */
+void gc_server_destroy(gc_server *s);
 
 /* Release a handle and its device memory (NULL is a no-op). */
 void gc_graph_free(gc_graph *g);

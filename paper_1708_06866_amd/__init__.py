@@ -36,7 +36,20 @@ GC_EDEVICE = -5
 GC_EOVERFLOW = -6
 GC_INPUT_ONE_BASED = 0x1
 
+GC_PENDING = 1
+
 _lib = None
+
+
+class GCRequest(ctypes.Structure):
+    _fields_ = [("graph_id", ctypes.c_int32), ("kind", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class GCResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("kind", ctypes.c_int32), ("value", ctypes.c_int64),
+                ("edges", ctypes.c_int64), ("t_submit", ctypes.c_double),
+                ("t_start", ctypes.c_double), ("t_done", ctypes.c_double)]
 
 
 class GCError(RuntimeError):
@@ -61,6 +74,12 @@ def lib():
         L.gc_edge_support.argtypes = [P, P, i64, P]
         L.gc_ktruss.argtypes = [P, i32, P, i64, P, ctypes.POINTER(i64)]
         L.gc_truss_decomposition.argtypes = [P, P, i64, P, ctypes.POINTER(i32)]
+        L.gc_graph_autotune.argtypes = [P, P, P, P]
+        L.gc_graph_set_strategy.argtypes = [P, P]
+        L.gc_graph_autotune.restype = i32
+        L.gc_graph_set_strategy.restype = i32
+        L.gc_graph_truss_stats.argtypes = [P, P, i32]
+        L.gc_graph_truss_stats.restype = i32
         L.gc_graph_free.argtypes = [P]
         L.gc_graph_free.restype = None
         L.gc_status_str.argtypes = [i32]
@@ -80,6 +99,18 @@ def lib():
         L.gc_batch_set_strategy.argtypes = [P, P]
         L.gc_batch_free.argtypes = [P]
         L.gc_batch_free.restype = None
+        L.gc_server_create.argtypes = [i64, ctypes.POINTER(P)]
+        L.gc_server_set_mode.argtypes = [P, i32]
+        L.gc_server_add_graph.argtypes = [P, P, P, i64, i32, ctypes.POINTER(i32)]
+        L.gc_server_submit.argtypes = [P, ctypes.POINTER(GCRequest), ctypes.POINTER(i64)]
+        L.gc_server_poll.argtypes = [P, i64, ctypes.POINTER(GCResult)]
+        L.gc_server_wait.argtypes = [P, i64, ctypes.POINTER(GCResult)]
+        L.gc_server_stats.argtypes = [P, P]
+        L.gc_server_destroy.argtypes = [P]
+        L.gc_server_destroy.restype = None
+        for name in ("gc_server_create", "gc_server_set_mode", "gc_server_add_graph",
+                     "gc_server_submit", "gc_server_poll", "gc_server_wait", "gc_server_stats"):
+            getattr(L, name).restype = i32
         for name in ("gc_build_csr", "gc_graph_info", "gc_graph_edges", "gc_graph_oriented",
                      "gc_triangle_count", "gc_edge_support", "gc_ktruss",
                      "gc_truss_decomposition", "gc_batch_build", "gc_batch_info",
@@ -177,6 +208,32 @@ class Graph:
 
     def truss_decomposition(self, out=None, stream=None):
         return gc_truss_decomposition(self, out, stream)
+
+    def autotune(self, stream=None):
+        """Per-bin count strategies chosen by timing: (strategy[5], ms[5, 5])."""
+        import numpy as np
+        st = np.zeros(5, dtype=np.int32)
+        ms = np.zeros(25, dtype=np.float32)
+        _check(lib().gc_graph_autotune(self.handle, _stream(stream),
+                                       ctypes.c_void_p(st.ctypes.data),
+                                       ctypes.c_void_p(ms.ctypes.data)), "gc_graph_autotune")
+        return st, ms.reshape(5, 5)
+
+    def truss_stats(self) -> dict:
+        """Counters of the last truss decomposition on this handle."""
+        import numpy as np
+        v = np.zeros(37, dtype=np.int64)
+        _check(lib().gc_graph_truss_stats(self.handle, ctypes.c_void_p(v.ctypes.data), 37),
+               "gc_graph_truss_stats")
+        return {"levels": int(v[0]), "rounds": int(v[1]), "removed": int(v[2]),
+                "largest_round": int(v[3]), "compactions": int(v[4]),
+                "rounds_by_log2_size": [int(x) for x in v[5:]]}
+
+    def set_strategy(self, strategy):
+        import numpy as np
+        st = np.ascontiguousarray(strategy, dtype=np.int32)
+        _check(lib().gc_graph_set_strategy(self.handle, ctypes.c_void_p(st.ctypes.data)),
+               "gc_graph_set_strategy")
 
 
 def _handle(g):
@@ -335,10 +392,10 @@ class Batch:
 
     def autotune(self, stream=None):
         st = _np.zeros(5, dtype=_np.int32)
-        ms = _np.zeros(15, dtype=_np.float32)
+        ms = _np.zeros(25, dtype=_np.float32)
         _check(lib().gc_batch_autotune(self.handle, _stream(stream), ctypes.c_void_p(st.ctypes.data),
                                        ctypes.c_void_p(ms.ctypes.data)), "gc_batch_autotune")
-        return st, ms.reshape(5, 3)
+        return st, ms.reshape(5, 5)
 
     def set_strategy(self, strategy):
         st = _np.ascontiguousarray(strategy, dtype=_np.int32)
@@ -376,3 +433,85 @@ def build_batch(graphs, device="cuda") -> Batch:
     s = torch.from_numpy(_np.concatenate(srcs) if srcs else _np.zeros(0, _np.int32)).to(device)
     d = torch.from_numpy(_np.concatenate(dsts) if dsts else _np.zeros(0, _np.int32)).to(device)
     return gc_batch_build(s, d, off, nv)
+
+
+# ----------------------------------------------------------------------------
+# serving
+# ----------------------------------------------------------------------------
+TRIANGLE_COUNT = 0
+KTRUSS_EDGES = 1
+
+
+class Server:
+    """A gc_server: registered graphs, queries with continuous batching."""
+
+    STAT_NAMES = ("completed", "batches", "max_batch", "builds", "evictions", "bytes_charged",
+                  "peak_bytes_charged", "deferred", "resident_graphs", "budget")
+
+    def __init__(self, budget_bytes: int, mode: int = 0):
+        torch.cuda.current_device()  # make sure the HIP runtime is up on this device
+        h = ctypes.c_void_p()
+        _check(lib().gc_server_create(int(budget_bytes), ctypes.byref(h)), "gc_server_create")
+        self._h = h
+        if mode:
+            self.set_mode(mode)
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("server already destroyed")
+        return self._h
+
+    def close(self):
+        if self._h:
+            lib().gc_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_mode(self, mode: int):
+        _check(lib().gc_server_set_mode(self.handle, int(mode)), "gc_server_set_mode")
+
+    def add_graph(self, src, dst, n_vertices: int) -> int:
+        s = _np.ascontiguousarray(src, dtype=_np.int32)
+        d = _np.ascontiguousarray(dst, dtype=_np.int32)
+        gid = ctypes.c_int32()
+        _check(lib().gc_server_add_graph(self.handle, ctypes.c_void_p(s.ctypes.data),
+                                         ctypes.c_void_p(d.ctypes.data), len(s), int(n_vertices),
+                                         ctypes.byref(gid)), "gc_server_add_graph")
+        return int(gid.value)
+
+    def submit(self, graph_id: int, kind: int = TRIANGLE_COUNT, k: int = 0) -> int:
+        req = GCRequest(int(graph_id), int(kind), int(k), 0)
+        t = ctypes.c_int64()
+        _check(lib().gc_server_submit(self.handle, ctypes.byref(req), ctypes.byref(t)),
+               "gc_server_submit")
+        return int(t.value)
+
+    @staticmethod
+    def _res(r: GCResult) -> dict:
+        return {"status": r.status, "kind": r.kind, "value": r.value, "edges": r.edges,
+                "t_submit": r.t_submit, "t_start": r.t_start, "t_done": r.t_done}
+
+    def poll(self, ticket: int):
+        r = GCResult()
+        st = lib().gc_server_poll(self.handle, int(ticket), ctypes.byref(r))
+        if st == GC_PENDING:
+            return None
+        _check(st, "gc_server_poll")
+        return self._res(r)
+
+    def wait(self, ticket: int) -> dict:
+        r = GCResult()
+        _check(lib().gc_server_wait(self.handle, int(ticket), ctypes.byref(r)), "gc_server_wait")
+        return self._res(r)
+
+    def stats(self) -> dict:
+        v = _np.zeros(10, dtype=_np.int64)
+        _check(lib().gc_server_stats(self.handle, ctypes.c_void_p(v.ctypes.data)),
+               "gc_server_stats")
+        return dict(zip(self.STAT_NAMES, (int(x) for x in v)))

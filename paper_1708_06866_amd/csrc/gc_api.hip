@@ -133,13 +133,68 @@ extern "C" gc_status gc_triangle_count(gc_graph *g, gc_stream stream, int64_t *h
     GC_TRY(g->ws.reserve(256));
     unsigned long long *d = g->ws.take<unsigned long long>(1);
     GC_HIP(hipMemsetAsync(d, 0, sizeof(unsigned long long), s));
-    GC_TRY(count_triangles(c, g->units, d, s));
+    GC_TRY(count_triangles_ex(c, g->units, d, nullptr, nullptr, g->strategy, s));
     unsigned long long h = 0;
     GC_HIP(hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, s));
     GC_HIP(hipStreamSynchronize(s));
     *h_count = (int64_t)h;
     return GC_OK;
   });
+}
+
+extern "C" gc_status gc_graph_autotune(gc_graph *g, gc_stream stream, int32_t *h_strategy,
+                                       float *h_ms) {
+  clear_error();
+  if (!g) {
+    set_error("gc_graph_autotune: NULL handle");
+    return GC_EINVAL;
+  }
+  return on_device(g, [&]() -> gc_status {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    float ms[kCountBins * kCountStrategies];
+    for (float &x : ms) x = -1.f;
+    if (g->m > 0) {
+      const CsrView c = g->csr.view(g->n, (int32_t)g->m);
+      if (!g->units_ready) {
+        GC_TRY(build_units(c, g->units, g->ws, s));
+        g->units_ready = true;
+      }
+      GC_TRY(g->ws.reserve(256));
+      unsigned long long *d = g->ws.take<unsigned long long>(1);
+      GC_TRY(autotune_bins(c, g->units, g->strategy, ms, d, nullptr, nullptr, s));
+      save_strategy_cache(g->device, g->strategy);
+    }
+    if (h_strategy)
+      for (int b = 0; b < kCountBins; ++b) h_strategy[b] = g->strategy[b];
+    if (h_ms)
+      for (int i = 0; i < kCountBins * kCountStrategies; ++i) h_ms[i] = ms[i];
+    return GC_OK;
+  });
+}
+
+extern "C" gc_status gc_graph_truss_stats(const gc_graph *g, int64_t *h_stats, int32_t cap) {
+  clear_error();
+  if (!g || !h_stats || cap < 0) {
+    set_error("gc_graph_truss_stats: invalid argument");
+    return GC_EINVAL;
+  }
+  for (int32_t i = 0; i < cap && i < 37; ++i) h_stats[i] = g->peel_stats[i];
+  return GC_OK;
+}
+
+extern "C" gc_status gc_graph_set_strategy(gc_graph *g, const int32_t *h_strategy) {
+  clear_error();
+  if (!g || !h_strategy) {
+    set_error("gc_graph_set_strategy: invalid argument");
+    return GC_EINVAL;
+  }
+  for (int b = 0; b < kCountBins; ++b)
+    if (!count_strategy_valid(b, h_strategy[b])) {
+      set_error("gc_graph_set_strategy: strategy not admissible for its bin");
+      return GC_EINVAL;
+    }
+  for (int b = 0; b < kCountBins; ++b) g->strategy[b] = h_strategy[b];
+  return GC_OK;
 }
 
 extern "C" gc_status gc_edge_support(gc_graph *g, int32_t *d_support, int64_t cap,

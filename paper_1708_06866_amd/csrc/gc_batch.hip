@@ -137,39 +137,6 @@ __global__ void k_mask_counts(const uint8_t *__restrict__ mask, const int32_t *_
 
 static unsigned gsz(int64_t work) { return grid_for(work, 256, 65536); }
 
-static std::string arch_name(int dev) {
-  hipDeviceProp_t p;
-  if (hipGetDeviceProperties(&p, dev) != hipSuccess) return "unknown";
-  std::string a = p.gcnArchName;
-  const size_t c = a.find(':');
-  return c == std::string::npos ? a : a.substr(0, c);
-}
-
-// Cache file lines: "<arch> <bin> <strategy>".
-static void load_tuning(gc_batch *b) {
-  const char *path = getenv("GC_AUTOTUNE_CACHE");
-  if (!path) return;
-  FILE *f = fopen(path, "r");
-  if (!f) return;
-  const std::string arch = arch_name(b->device);
-  char a[128];
-  int bin, st;
-  while (fscanf(f, "%127s %d %d", a, &bin, &st) == 3)
-    if (arch == a && bin >= 0 && bin < kCountBins && count_strategy_valid(bin, st))
-      b->strategy[bin] = st;
-  fclose(f);
-}
-
-static void save_tuning(const gc_batch *b) {
-  const char *path = getenv("GC_AUTOTUNE_CACHE");
-  if (!path) return;
-  FILE *f = fopen(path, "w");
-  if (!f) return;
-  const std::string arch = arch_name(b->device);
-  for (int bin = 0; bin < kCountBins; ++bin) fprintf(f, "%s %d %d\n", arch.c_str(), bin, b->strategy[bin]);
-  fclose(f);
-}
-
 static gc_status batch_units(gc_batch *b, hipStream_t s) {
   gc_graph *g = b->g;
   if (!g->units_ready && g->m > 0) {
@@ -291,7 +258,7 @@ extern "C" gc_status gc_batch_build(const int32_t *d_src, const int32_t *d_dst,
                      hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return fail(GC_EDEVICE);
-  load_tuning(b);
+  load_strategy_cache(b->device, b->strategy);
   *out = b;
   return GC_OK;
 }
@@ -335,41 +302,11 @@ extern "C" gc_status gc_batch_autotune(gc_batch *b, gc_stream stream, int32_t *h
   gc_graph *g = b->g;
   b->drop_graph();
   if (g->m > 0) {
-    const CsrView c = g->csr.view(g->n, (int32_t)g->m);
-    unsigned long long *tb = static_cast<unsigned long long *>(b->tbuf.ptr);
-    const int32_t *gor = static_cast<const int32_t *>(b->graph_of_rank.ptr);
-    hipEvent_t e0, e1;
-    GC_HIP(hipEventCreate(&e0));
-    GC_HIP(hipEventCreate(&e1));
-    for (int bin = 0; bin < kCountBins; ++bin) {
-      if (g->units.bin_count[bin] == 0) continue;
-      float best = 0;
-      int best_st = b->strategy[bin];
-      for (int st = 0; st < kCountStrategies; ++st) {
-        b->tuned_ms[bin][st] = -1.f;
-        if (!count_strategy_valid(bin, st)) continue;
-        float ms = 0;
-        for (int rep = 0; rep < 3; ++rep) {  // first run warms caches
-          GC_HIP(hipEventRecord(e0, s));
-          GC_TRY(count_bin(c, g->units, bin, st, nullptr, tb, gor, s));
-          GC_HIP(hipEventRecord(e1, s));
-          GC_HIP(hipEventSynchronize(e1));
-          float t = 0;
-          GC_HIP(hipEventElapsedTime(&t, e0, e1));
-          if (rep > 0) ms += t;
-        }
-        b->tuned_ms[bin][st] = ms / 2;
-        if (best == 0 || ms / 2 < best) {
-          best = ms / 2;
-          best_st = st;
-        }
-      }
-      b->strategy[bin] = best_st;
-    }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    GC_TRY(autotune_bins(g->csr.view(g->n, (int32_t)g->m), g->units, b->strategy, &b->tuned_ms[0][0],
+                         nullptr, static_cast<unsigned long long *>(b->tbuf.ptr),
+                         static_cast<const int32_t *>(b->graph_of_rank.ptr), s));
   }
-  save_tuning(b);
+  save_strategy_cache(b->device, b->strategy);
   if (h_strategy)
     for (int bin = 0; bin < kCountBins; ++bin) h_strategy[bin] = b->strategy[bin];
   if (h_ms)

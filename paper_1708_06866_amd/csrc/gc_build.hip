@@ -327,6 +327,7 @@ extern "C" gc_status gc_build_csr(const int32_t *d_src, const int32_t *d_dst, in
     delete g;
     return GC_EDEVICE;
   }
+  gc::load_strategy_cache(g->device, g->strategy);
   gc_status st = gc::build_impl(d_src, d_dst, n_pairs, n_vertices, flags,
                                 static_cast<hipStream_t>(stream), g);
   if (st != GC_OK) {

@@ -8,18 +8,29 @@
 // the triangle exists iff c is also in N+(b).  A work unit is (b, a chunk of
 // b's in-list): the block stages N+(b) once in an LDS hash table, then its
 // waves stream the tails of the chunk's in-edges, one tail per wave, 64
-// consecutive elements per step (coalesced), probing each element.
+// consecutive elements per step (coalesced), 4 steps in flight per lane.
 //
-// Degree bins pick the table: d+(b) <= 32, 256, 2048 and 8192 (count) /
-// 4096 (support) use LDS tables of 64, 512, 4096 and 16384 / 8192 slots
-// (load factor <= 1/2, linear probing); larger out-lists are binary-searched
-// in place in global memory.
+// The LDS table is bucketed: 4 slots per 16-byte bucket, filled in slot
+// order, linear probing over buckets.  A probe reads one bucket
+// (ds_read_b128) and compares 4 keys; the key is absent as soon as a bucket
+// with a free slot is seen, so almost every probe ends after one read.  The
+// reads of the 4 in-flight elements are issued together.
+//
+// Degree bins pick the table size: d+(b) <= 32, 256, 2048 and 8192 (count) /
+// 4096 (support) with at most half the slots used (strategy 0) or a quarter
+// (strategy 1); longer out-lists are binary-searched in HBM (strategy 2, the
+// only one for the last bin).
 //
 // Support: a hit (a, b, c) adds one to each of its three edges.  a -> b (the
 // in-edge) is summed over the wave and added once per in-edge; b -> c (the
-// staged edge) is counted in an LDS counter beside the table entry and
+// staged edge) is counted in an LDS counter beside the table slot and
 // flushed once per unit; a -> c (the streamed element) takes one global
 // atomic.
+#include <stdio.h>
+#include <stdlib.h>
+
+#include <string>
+
 #include "gc_graph.h"
 
 namespace gc {
@@ -28,7 +39,7 @@ constexpr int CBLK = 256;
 constexpr int CWAVES = CBLK / 64;
 constexpr int UNIT_CHUNK = 128;  // in-edges per work unit
 constexpr int NBINS = 5;
-constexpr int TC_UNROLL = 4;     // tail loads in flight per lane
+constexpr int TC_UNROLL = 4;     // tail elements in flight per lane
 
 // Out-degree bounds of the bins (inclusive); the last bin is unbounded.
 __host__ __device__ constexpr int bin_limit_count(int b) {
@@ -37,9 +48,149 @@ __host__ __device__ constexpr int bin_limit_count(int b) {
 __host__ __device__ constexpr int bin_limit_support(int b) {
   return b == 0 ? 32 : b == 1 ? 256 : b == 2 ? 2048 : b == 3 ? 4096 : 0x7fffffff;
 }
+// log2 of the bucket count holding a bin's out-lists at load <= 1/2
+__host__ __device__ constexpr int bin_logb_count(int b) {
+  return b == 0 ? 4 : b == 1 ? 7 : b == 2 ? 10 : 12;
+}
+__host__ __device__ constexpr int bin_logb_support(int b) {
+  return b == 0 ? 4 : b == 1 ? 7 : b == 2 ? 10 : 11;
+}
 
-__device__ __forceinline__ uint32_t hslot(int32_t w, int logh) {
-  return ((uint32_t)w * 0x9E3779B1u) >> (32 - logh);
+__device__ __forceinline__ uint32_t hash_to(int32_t w, int logn) {
+  return ((uint32_t)w * 0x9E3779B1u) >> (32 - logn);
+}
+
+// ---- LDS hash tables -------------------------------------------------------
+// Both keep non-negative keys; -1 marks a free slot.  They are filled by the
+// whole block (after clear + barrier) and only read afterwards.
+
+// Linear probing, one key per 4-byte slot, 1 << LOGS slots.
+template <int LOGS>
+struct LinTable {
+  static constexpr int SLOTS = 1 << LOGS;
+  using Probe = int32_t;
+  __device__ static void clear(int32_t *t) {
+    for (int i = threadIdx.x; i < SLOTS; i += CBLK) t[i] = -1;
+  }
+  __device__ static int32_t insert(int32_t *t, int32_t w) {
+    uint32_t h = hash_to(w, LOGS);
+    while (atomicCAS(&t[h], -1, w) != -1) h = (h + 1) & (SLOTS - 1);
+    return (int32_t)h;
+  }
+  __device__ static Probe first(const int32_t *t, int32_t w) { return t[hash_to(w, LOGS)]; }
+  // slot holding w, or -1; `x` is the value read at w's home slot
+  __device__ static int32_t find(const int32_t *t, int32_t w, Probe x) {
+    uint32_t h = hash_to(w, LOGS);
+    for (;;) {
+      if (x == w) return (int32_t)h;
+      if (x < 0) return -1;
+      h = (h + 1) & (SLOTS - 1);
+      x = t[h];
+    }
+  }
+};
+
+// Buckets of 4 slots (16 bytes, one ds_read_b128 per bucket), 1 << LOGB
+// buckets, slots of a bucket filled in order, linear probing over buckets: a
+// key is absent as soon as a bucket with a free slot is seen.
+template <int LOGB>
+struct BucketTable {
+  static constexpr int SLOTS = 4 << LOGB;
+  using Probe = int4;
+  __device__ static void clear(int32_t *t) {
+    int4 *b = reinterpret_cast<int4 *>(t);
+    for (int i = threadIdx.x; i < (1 << LOGB); i += CBLK) b[i] = make_int4(-1, -1, -1, -1);
+  }
+  __device__ static int32_t insert(int32_t *t, int32_t w) {
+    uint32_t b = hash_to(w, LOGB);
+    for (;;) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (atomicCAS(&t[b * 4 + k], -1, w) == -1) return (int32_t)(b * 4 + k);
+      b = (b + 1) & ((1u << LOGB) - 1);
+    }
+  }
+  __device__ static Probe first(const int32_t *t, int32_t w) {
+    return reinterpret_cast<const int4 *>(t)[hash_to(w, LOGB)];
+  }
+  __device__ static int32_t find(const int32_t *t, int32_t w, Probe k) {
+    uint32_t b = hash_to(w, LOGB);
+    for (;;) {
+      if (k.x == w) return (int32_t)(b * 4);
+      if (k.y == w) return (int32_t)(b * 4 + 1);
+      if (k.z == w) return (int32_t)(b * 4 + 2);
+      if (k.w == w) return (int32_t)(b * 4 + 3);
+      if (k.w < 0) return -1;
+      b = (b + 1) & ((1u << LOGB) - 1);
+      k = reinterpret_cast<const int4 *>(t)[b];
+    }
+  }
+};
+
+// ---- streaming the tails (software-pipelined) -----------------------------
+// A wave walks its in-edges j = j0, j0 + 4, ... < j1.  An "item" is one
+// 64 * TC_UNROLL element chunk of one in-edge's tail.  The loads of the next
+// item are issued before the current item is probed, so every wave keeps two
+// rounds of tail loads in flight while it works on the LDS table.
+struct Item {
+  int32_t j;   // in-edge (wave-uniform)
+  int2 t;      // its tail range
+  int32_t o;   // chunk start
+};
+
+__device__ __forceinline__ Item first_item(const CsrView &c, int32_t j, int32_t j1) {
+  Item it;
+  it.t = make_int2(0, 0);
+  for (; j < j1; j += CWAVES) {
+    it.t = c.in_tail[j];
+    if (it.t.x < it.t.y) break;
+  }
+  it.j = j;
+  it.o = it.t.x;
+  return it;
+}
+
+__device__ __forceinline__ Item next_item(const CsrView &c, Item it, int32_t j1) {
+  it.o += 64 * TC_UNROLL;
+  if (it.o < it.t.y) return it;
+  Item n = first_item(c, it.j + CWAVES, j1);
+  return n;
+}
+
+__device__ __forceinline__ void load_item(const CsrView &c, const Item &it, int32_t j1, int lane,
+                                          int32_t (&w)[TC_UNROLL]) {
+#pragma unroll
+  for (int u = 0; u < TC_UNROLL; ++u) {
+    const int32_t p = it.o + 64 * u + lane;
+    w[u] = (it.j < j1 && p < it.t.y) ? c.col[p] : -1;
+  }
+}
+
+template <class TB>
+__device__ __forceinline__ int32_t probe_pipe(const int32_t *tab, const CsrView &c, int32_t j0,
+                                              int32_t j1, int lane) {
+  int32_t hits = 0;
+  Item it = first_item(c, j0, j1);
+  if (it.j >= j1) return 0;
+  int32_t w[TC_UNROLL];
+  load_item(c, it, j1, lane, w);
+  for (;;) {
+    const Item nx = next_item(c, it, j1);
+    int32_t wn[TC_UNROLL];
+    load_item(c, nx, j1, lane, wn);   // in flight while we probe
+    typename TB::Probe q[TC_UNROLL];
+#pragma unroll
+    for (int u = 0; u < TC_UNROLL; ++u)
+      if (w[u] >= 0) q[u] = TB::first(tab, w[u]);
+#pragma unroll
+    for (int u = 0; u < TC_UNROLL; ++u)
+      if (w[u] >= 0 && TB::find(tab, w[u], q[u]) >= 0) ++hits;
+    if (nx.j >= j1) break;
+    it = nx;
+#pragma unroll
+    for (int u = 0; u < TC_UNROLL; ++u) w[u] = wn[u];
+  }
+  return hits;
 }
 
 // ----------------------------------------------------------------------------
@@ -136,65 +287,38 @@ struct CountOut {
   const int32_t *graph_of_rank = nullptr;
 };
 
-__device__ __forceinline__ void flush_unit(const CountOut &o, int32_t v, int32_t hits,
-                                           unsigned long long &total, int lane) {
-  const int32_t s = wave_sum_i32(hits);
-  if (o.per_graph) {
-    if (lane == 0 && s) atomicAdd(&o.per_graph[o.graph_of_rank[v]], (unsigned long long)s);
-  } else {
-    total += (unsigned)s;
-  }
+// Stage N+(v) (slots [rb, re) of col) into the table; returns after a barrier.
+template <class TB>
+__device__ __forceinline__ void stage_row(int32_t *tab, const int32_t *__restrict__ col, int32_t rb,
+                                          int32_t re) {
+  TB::clear(tab);
+  __syncthreads();
+  for (int32_t i = rb + threadIdx.x; i < re; i += CBLK) TB::insert(tab, col[i]);
+  __syncthreads();
 }
 
-template <int LOGH>
-__global__ __launch_bounds__(CBLK) void k_tc_hash(CsrView c, const int4 *__restrict__ units,
-                                                  int64_t nunits, CountOut out) {
-  constexpr int H = 1 << LOGH;
-  __shared__ int32_t tab[H];
+template <class TB>
+__global__ __launch_bounds__(CBLK) void k_tc_lds(CsrView c, const int4 *__restrict__ units,
+                                                 int64_t nunits, CountOut out) {
+  __shared__ int4 mem[TB::SLOTS / 4];
+  int32_t *tab = reinterpret_cast<int32_t *>(mem);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   unsigned long long total = 0;  // wave-uniform
   for (int64_t ui = blockIdx.x; ui < nunits; ui += gridDim.x) {
     const int4 U = units[ui];
-    const int32_t rb = c.row_ptr[U.x], re = c.row_ptr[U.x + 1];
-    for (int i = threadIdx.x; i < H; i += CBLK) tab[i] = -1;
-    __syncthreads();
-    for (int32_t i = rb + threadIdx.x; i < re; i += CBLK) {
-      const int32_t w = c.col[i];
-      uint32_t h = hslot(w, LOGH);
-      while (atomicCAS(&tab[h], -1, w) != -1) h = (h + 1) & (H - 1);
+    stage_row<TB>(tab, c.col, c.row_ptr[U.x], c.row_ptr[U.x + 1]);
+    const int32_t sum = wave_sum_i32(probe_pipe<TB>(tab, c, U.y + wave, U.z, lane));
+    if (out.per_graph) {
+      if (lane == 0 && sum) atomicAdd(&out.per_graph[out.graph_of_rank[U.x]], (unsigned long long)sum);
+    } else {
+      total += (unsigned)sum;
     }
-    __syncthreads();
-    int32_t hits = 0;
-    int32_t j = U.y + wave;
-    int2 t = j < U.z ? c.in_tail[j] : make_int2(0, 0);
-    for (; j < U.z; j += CWAVES) {
-      // prefetch the next in-edge's tail range while this one streams
-      const int2 tn = j + CWAVES < U.z ? c.in_tail[j + CWAVES] : make_int2(0, 0);
-      for (int32_t p = t.x + lane; p < t.y; p += 64 * TC_UNROLL) {
-        int32_t w[TC_UNROLL];
-#pragma unroll
-        for (int k = 0; k < TC_UNROLL; ++k) w[k] = p + 64 * k < t.y ? c.col[p + 64 * k] : -1;
-#pragma unroll
-        for (int k = 0; k < TC_UNROLL; ++k) {
-          if (w[k] < 0) continue;
-          uint32_t h = hslot(w[k], LOGH);
-          for (;;) {
-            const int32_t x = tab[h];
-            if (x == w[k]) { ++hits; break; }
-            if (x < 0) break;
-            h = (h + 1) & (H - 1);
-          }
-        }
-      }
-      t = tn;
-    }
-    flush_unit(out, U.x, hits, total, lane);
     __syncthreads();
   }
   if (!out.per_graph && lane == 0 && total) atomicAdd(out.total, total);
 }
 
-// Out-lists too long for LDS: binary search in the sorted row in global memory.
+// Out-lists too long for LDS: binary search in the sorted row in HBM.
 __global__ __launch_bounds__(CBLK) void k_tc_search(CsrView c, const int4 *__restrict__ units,
                                                     int64_t nunits, CountOut out) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -215,7 +339,12 @@ __global__ __launch_bounds__(CBLK) void k_tc_search(CsrView c, const int4 *__res
         hits += (lo < re && c.col[lo] == w) ? 1 : 0;
       }
     }
-    flush_unit(out, U.x, hits, total, lane);
+    const int32_t sum = wave_sum_i32(hits);
+    if (out.per_graph) {
+      if (lane == 0 && sum) atomicAdd(&out.per_graph[out.graph_of_rank[U.x]], (unsigned long long)sum);
+    } else {
+      total += (unsigned)sum;
+    }
   }
   if (!out.per_graph && lane == 0 && total) atomicAdd(out.total, total);
 }
@@ -226,29 +355,54 @@ static unsigned unit_grid(int64_t nunits, int per_cu) {
   return (unsigned)(g < 1 ? 1 : g);
 }
 
-// Strategies per bin: 0 = LDS hash at the bin's table size (load <= 1/2),
-// 1 = LDS hash with a table twice as large (load <= 1/4), 2 = binary search
-// in HBM.  The last bin only admits 2.
+// Strategies per bin (the autotuner's search space):
+//   0 linear-probing table, load <= 1/2     1 linear-probing table, load <= 1/4
+//   2 binary search in HBM                  3 bucketed table, load <= 1/2
+//   4 bucketed table, load <= 1/4
+// The last (unbounded) bin only admits 2.
 bool count_strategy_valid(int bin, int strategy) {
   if (strategy == 2) return true;
-  return bin < NBINS - 1 && (strategy == 0 || strategy == 1);
+  return bin < NBINS - 1 && strategy >= 0 && strategy < kCountStrategies;
+}
+
+template <class TB>
+static void launch_tc_lds(const CsrView &c, const int4 *ub, int64_t nu, const CountOut &o,
+                          hipStream_t s) {
+  constexpr int bytes = TB::SLOTS * 4;
+  constexpr int per_cu = bytes <= 8192 ? 16 : bytes <= 16384 ? 8 : bytes <= 32768 ? 4 : bytes <= 65536 ? 2 : 1;
+  k_tc_lds<TB><<<unit_grid(nu, per_cu), CBLK, 0, s>>>(c, ub, nu, o);
+}
+
+// log2 of linear-probing slots at load <= 1/2 per bin
+__host__ __device__ constexpr int bin_logs_count(int b) {
+  return b == 0 ? 6 : b == 1 ? 9 : b == 2 ? 12 : 14;
 }
 
 static gc_status launch_count_bin(const CsrView &c, const int4 *ub, int64_t nu, int b,
                                   int strategy, const CountOut &o, hipStream_t s) {
   if (strategy == 2 || b == NBINS - 1) {
     k_tc_search<<<unit_grid(nu, 8), CBLK, 0, s>>>(c, ub, nu, o);
+  } else if (strategy == 0 || strategy == 1) {
+    switch (bin_logs_count(b) + (strategy == 1 ? 1 : 0)) {
+      case 6: launch_tc_lds<LinTable<6>>(c, ub, nu, o, s); break;
+      case 7: launch_tc_lds<LinTable<7>>(c, ub, nu, o, s); break;
+      case 9: launch_tc_lds<LinTable<9>>(c, ub, nu, o, s); break;
+      case 10: launch_tc_lds<LinTable<10>>(c, ub, nu, o, s); break;
+      case 12: launch_tc_lds<LinTable<12>>(c, ub, nu, o, s); break;
+      case 13: launch_tc_lds<LinTable<13>>(c, ub, nu, o, s); break;
+      case 14: launch_tc_lds<LinTable<14>>(c, ub, nu, o, s); break;
+      default: launch_tc_lds<LinTable<15>>(c, ub, nu, o, s); break;
+    }
   } else {
-    const int logh = (b == 0 ? 6 : b == 1 ? 9 : b == 2 ? 12 : 14) + (strategy == 1 ? 1 : 0);
-    switch (logh) {
-      case 6: k_tc_hash<6><<<unit_grid(nu, 16), CBLK, 0, s>>>(c, ub, nu, o); break;
-      case 7: k_tc_hash<7><<<unit_grid(nu, 16), CBLK, 0, s>>>(c, ub, nu, o); break;
-      case 9: k_tc_hash<9><<<unit_grid(nu, 16), CBLK, 0, s>>>(c, ub, nu, o); break;
-      case 10: k_tc_hash<10><<<unit_grid(nu, 16), CBLK, 0, s>>>(c, ub, nu, o); break;
-      case 12: k_tc_hash<12><<<unit_grid(nu, 8), CBLK, 0, s>>>(c, ub, nu, o); break;
-      case 13: k_tc_hash<13><<<unit_grid(nu, 4), CBLK, 0, s>>>(c, ub, nu, o); break;
-      case 14: k_tc_hash<14><<<unit_grid(nu, 4), CBLK, 0, s>>>(c, ub, nu, o); break;
-      default: k_tc_hash<15><<<unit_grid(nu, 2), CBLK, 0, s>>>(c, ub, nu, o); break;
+    switch (bin_logb_count(b) + (strategy == 4 ? 1 : 0)) {
+      case 4: launch_tc_lds<BucketTable<4>>(c, ub, nu, o, s); break;
+      case 5: launch_tc_lds<BucketTable<5>>(c, ub, nu, o, s); break;
+      case 7: launch_tc_lds<BucketTable<7>>(c, ub, nu, o, s); break;
+      case 8: launch_tc_lds<BucketTable<8>>(c, ub, nu, o, s); break;
+      case 10: launch_tc_lds<BucketTable<10>>(c, ub, nu, o, s); break;
+      case 11: launch_tc_lds<BucketTable<11>>(c, ub, nu, o, s); break;
+      case 12: launch_tc_lds<BucketTable<12>>(c, ub, nu, o, s); break;
+      default: launch_tc_lds<BucketTable<13>>(c, ub, nu, o, s); break;
     }
   }
   GC_LAUNCH_CHECK();
@@ -290,58 +444,226 @@ gc_status count_triangles(const CsrView &c, const UnitStore &u, unsigned long lo
   return count_triangles_ex(c, u, d_count, nullptr, nullptr, nullptr, s);
 }
 
+gc_status autotune_bins(const CsrView &c, const UnitStore &u, int *strategy, float *ms,
+                        unsigned long long *d_total, unsigned long long *d_per_graph,
+                        const int32_t *graph_of_rank, hipStream_t s) {
+  for (int i = 0; i < kCountBins * kCountStrategies; ++i) ms[i] = -1.f;
+  if (c.m == 0) return GC_OK;
+  hipEvent_t e0, e1;
+  GC_HIP(hipEventCreate(&e0));
+  GC_HIP(hipEventCreate(&e1));
+  gc_status st = GC_OK;
+  for (int bin = 0; bin < kCountBins && st == GC_OK; ++bin) {
+    if (u.bin_count[bin] == 0) continue;
+    float best = -1.f;
+    for (int k = 0; k < kCountStrategies && st == GC_OK; ++k) {
+      if (!count_strategy_valid(bin, k)) continue;
+      float acc = 0;
+      for (int rep = 0; rep < 3 && st == GC_OK; ++rep) {  // the first run warms caches
+        if (hipEventRecord(e0, s) != hipSuccess) { st = GC_EDEVICE; break; }
+        st = count_bin(c, u, bin, k, d_total, d_per_graph, graph_of_rank, s);
+        if (st != GC_OK) break;
+        float t = 0;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
+          st = GC_EDEVICE;
+          break;
+        }
+        if (rep > 0) acc += t;
+      }
+      if (st != GC_OK) break;
+      ms[bin * kCountStrategies + k] = acc / 2;
+      if (best < 0 || acc / 2 < best) {
+        best = acc / 2;
+        strategy[bin] = k;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return st;
+}
+
+static std::string arch_of(int dev) {
+  hipDeviceProp_t p;
+  if (hipGetDeviceProperties(&p, dev) != hipSuccess) return "unknown";
+  std::string a = p.gcnArchName;
+  const size_t c = a.find(':');
+  return c == std::string::npos ? a : a.substr(0, c);
+}
+
+// Lines "<arch> <bin> <strategy>".
+void load_strategy_cache(int device, int *strategy) {
+  const char *path = getenv("GC_AUTOTUNE_CACHE");
+  if (!path) return;
+  FILE *f = fopen(path, "r");
+  if (!f) return;
+  const std::string arch = arch_of(device);
+  char a[128];
+  int bin, st;
+  while (fscanf(f, "%127s %d %d", a, &bin, &st) == 3)
+    if (arch == a && bin >= 0 && bin < kCountBins && count_strategy_valid(bin, st))
+      strategy[bin] = st;
+  fclose(f);
+}
+
+void save_strategy_cache(int device, const int *strategy) {
+  const char *path = getenv("GC_AUTOTUNE_CACHE");
+  if (!path) return;
+  FILE *f = fopen(path, "w");
+  if (!f) return;
+  const std::string arch = arch_of(device);
+  for (int bin = 0; bin < kCountBins; ++bin) fprintf(f, "%s %d %d\n", arch.c_str(), bin, strategy[bin]);
+  fclose(f);
+}
+
+// ----------------------------------------------------------------------------
+// Many graphs (separately built handles) in one launch per bin
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ int32_t find_graph(const int64_t *__restrict__ pre, int32_t nh,
+                                              int64_t ui) {
+  int32_t lo = 0, hi = nh + 1;  // upper bound of ui in pre[0..nh]
+  while (lo < hi) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (pre[mid] <= ui) lo = mid + 1; else hi = mid;
+  }
+  return lo - 1;
+}
+
+template <class TB>
+__global__ __launch_bounds__(CBLK) void k_tc_lds_multi(const GraphDesc *__restrict__ d,
+                                                       const int64_t *__restrict__ pre,
+                                                       int32_t nh, int bin,
+                                                       unsigned long long *__restrict__ out) {
+  __shared__ int4 mem[TB::SLOTS / 4];
+  int32_t *tab = reinterpret_cast<int32_t *>(mem);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t total = pre[nh];
+  for (int64_t ui = blockIdx.x; ui < total; ui += gridDim.x) {
+    const int32_t g = find_graph(pre, nh, ui);
+    const CsrView c = d[g].c;
+    const int4 U = d[g].units[d[g].bin_begin[bin] + (ui - pre[g])];
+    stage_row<TB>(tab, c.col, c.row_ptr[U.x], c.row_ptr[U.x + 1]);
+    const int32_t sum = wave_sum_i32(probe_pipe<TB>(tab, c, U.y + wave, U.z, lane));
+    if (lane == 0 && sum) atomicAdd(&out[g], (unsigned long long)sum);
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(CBLK) void k_tc_search_multi(const GraphDesc *__restrict__ d,
+                                                          const int64_t *__restrict__ pre,
+                                                          int32_t nh, int bin,
+                                                          unsigned long long *__restrict__ out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t total = pre[nh];
+  for (int64_t ui = blockIdx.x; ui < total; ui += gridDim.x) {
+    const int32_t g = find_graph(pre, nh, ui);
+    const CsrView c = d[g].c;
+    const int4 U = d[g].units[d[g].bin_begin[bin] + (ui - pre[g])];
+    const int32_t rb = c.row_ptr[U.x], re = c.row_ptr[U.x + 1];
+    int32_t hits = 0;
+    for (int32_t j = U.y + wave; j < U.z; j += CWAVES) {
+      const int2 t = c.in_tail[j];
+      for (int32_t p = t.x + lane; p < t.y; p += 64) {
+        const int32_t w = c.col[p];
+        int32_t lo = rb, hi = re;
+        while (lo < hi) {
+          const int32_t mid = lo + ((hi - lo) >> 1);
+          if (c.col[mid] < w) lo = mid + 1; else hi = mid;
+        }
+        hits += (lo < re && c.col[lo] == w) ? 1 : 0;
+      }
+    }
+    const int32_t sum = wave_sum_i32(hits);
+    if (lane == 0 && sum) atomicAdd(&out[g], (unsigned long long)sum);
+  }
+}
+
+__global__ void k_zero_counts(unsigned long long *__restrict__ x, int32_t n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) x[i] = 0;
+}
+
+gc_status count_multi_launch(const GraphDesc *d_desc, const int64_t *d_pre, const int64_t *h_pre,
+                             int32_t nh, unsigned long long *d_out, hipStream_t s) {
+  k_zero_counts<<<grid_for(nh, 256, 1024), 256, 0, s>>>(d_out, nh);
+  GC_LAUNCH_CHECK();
+  for (int b = 0; b < NBINS; ++b) {
+    const int64_t nu = h_pre[(int64_t)b * (nh + 1) + nh];
+    if (nu == 0) continue;
+    const int64_t *pre = d_pre + (int64_t)b * (nh + 1);
+    if (b == NBINS - 1) {
+      k_tc_search_multi<<<unit_grid(nu, 8), CBLK, 0, s>>>(d_desc, pre, nh, b, d_out);
+    } else {
+      switch (b) {
+        case 0: k_tc_lds_multi<LinTable<6>><<<unit_grid(nu, 16), CBLK, 0, s>>>(d_desc, pre, nh, b, d_out); break;
+        case 1: k_tc_lds_multi<LinTable<9>><<<unit_grid(nu, 16), CBLK, 0, s>>>(d_desc, pre, nh, b, d_out); break;
+        case 2: k_tc_lds_multi<LinTable<12>><<<unit_grid(nu, 8), CBLK, 0, s>>>(d_desc, pre, nh, b, d_out); break;
+        default: k_tc_lds_multi<LinTable<14>><<<unit_grid(nu, 2), CBLK, 0, s>>>(d_desc, pre, nh, b, d_out); break;
+      }
+    }
+    GC_LAUNCH_CHECK();
+  }
+  return GC_OK;
+}
+
 // ----------------------------------------------------------------------------
 // Per-slot support
 // ----------------------------------------------------------------------------
-template <int LOGH>
-__global__ __launch_bounds__(CBLK) void k_sup_hash(CsrView c, const int4 *__restrict__ units,
-                                                   int64_t nunits, int32_t *__restrict__ sup) {
-  constexpr int H = 1 << LOGH;
-  __shared__ int32_t tab[H];
-  __shared__ int32_t tslot[H];
-  __shared__ int32_t tcnt[H];
+template <int LOGS>
+__global__ __launch_bounds__(CBLK) void k_sup_lds(CsrView c, const int4 *__restrict__ units,
+                                                  int64_t nunits, int32_t *__restrict__ sup) {
+  using TB = LinTable<LOGS>;
+  constexpr int NS = TB::SLOTS;
+  __shared__ int4 mem[NS / 4];
+  __shared__ int32_t tslot[NS];  // oriented slot of the staged edge b -> c
+  __shared__ int32_t tcnt[NS];   // hits on that edge within this unit
+  int32_t *tab = reinterpret_cast<int32_t *>(mem);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int64_t ui = blockIdx.x; ui < nunits; ui += gridDim.x) {
     const int4 U = units[ui];
     const int32_t rb = c.row_ptr[U.x], re = c.row_ptr[U.x + 1];
-    for (int i = threadIdx.x; i < H; i += CBLK) { tab[i] = -1; tcnt[i] = 0; }
+    TB::clear(tab);
+    for (int i = threadIdx.x; i < NS; i += CBLK) tcnt[i] = 0;
     __syncthreads();
-    for (int32_t i = rb + threadIdx.x; i < re; i += CBLK) {
-      const int32_t w = c.col[i];
-      uint32_t h = hslot(w, LOGH);
-      while (atomicCAS(&tab[h], -1, w) != -1) h = (h + 1) & (H - 1);
-      tslot[h] = i;
-    }
+    for (int32_t i = rb + threadIdx.x; i < re; i += CBLK) tslot[TB::insert(tab, c.col[i])] = i;
     __syncthreads();
-    for (int32_t j = U.y + wave; j < U.z; j += CWAVES) {
-      const int2 t = c.in_tail[j];
-      int32_t mine = 0;
-      for (int32_t p = t.x + lane; p < t.y; p += 64 * TC_UNROLL) {
-        int32_t w[TC_UNROLL];
+    const int32_t j1 = U.z;
+    Item it = first_item(c, U.y + wave, j1);
+    if (it.j < j1) {
+      int32_t w[TC_UNROLL];
+      load_item(c, it, j1, lane, w);
+      int32_t mine = 0;  // hits of the current in-edge (edge a -> b)
+      for (;;) {
+        const Item nx = next_item(c, it, j1);
+        int32_t wn[TC_UNROLL];
+        load_item(c, nx, j1, lane, wn);
+        typename TB::Probe q[TC_UNROLL];
 #pragma unroll
-        for (int k = 0; k < TC_UNROLL; ++k) w[k] = p + 64 * k < t.y ? c.col[p + 64 * k] : -1;
+        for (int u = 0; u < TC_UNROLL; ++u)
+          if (w[u] >= 0) q[u] = TB::first(tab, w[u]);
 #pragma unroll
-        for (int k = 0; k < TC_UNROLL; ++k) {
-          if (w[k] < 0) continue;
-          uint32_t h = hslot(w[k], LOGH);
-          for (;;) {
-            const int32_t x = tab[h];
-            if (x == w[k]) {
-              ++mine;
-              atomicAdd(&tcnt[h], 1);             // edge b -> c
-              atomicAdd(&sup[p + 64 * k], 1);     // edge a -> c
-              break;
-            }
-            if (x < 0) break;
-            h = (h + 1) & (H - 1);
+        for (int u = 0; u < TC_UNROLL; ++u) {
+          if (w[u] < 0) continue;
+          const int32_t at = TB::find(tab, w[u], q[u]);
+          if (at >= 0) {
+            ++mine;
+            atomicAdd(&tcnt[at], 1);                            // edge b -> c
+            atomicAdd(&sup[it.o + 64 * u + lane], 1);           // edge a -> c
           }
         }
+        if (nx.j != it.j) {  // the in-edge is complete
+          const int32_t tot = wave_sum_i32(mine);
+          if (lane == 0 && tot) atomicAdd(&sup[c.in_slot[it.j]], tot);
+          mine = 0;
+        }
+        if (nx.j >= j1) break;
+        it = nx;
+#pragma unroll
+        for (int u = 0; u < TC_UNROLL; ++u) w[u] = wn[u];
       }
-      const int32_t tot = wave_sum_i32(mine);
-      if (lane == 0 && tot) atomicAdd(&sup[c.in_slot[j]], tot);  // edge a -> b
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < H; i += CBLK)
+    for (int i = threadIdx.x; i < NS; i += CBLK)
       if (tcnt[i]) atomicAdd(&sup[tslot[i]], tcnt[i]);
     __syncthreads();
   }
@@ -382,10 +704,10 @@ gc_status slot_support(const CsrView &c, const UnitStore &u, int32_t *d_sup, hip
     if (nu == 0) continue;
     const int4 *ub = units + u.bin_begin[b];
     switch (b) {
-      case 0: k_sup_hash<6><<<unit_grid(nu, 16), CBLK, 0, s>>>(c, ub, nu, d_sup); break;
-      case 1: k_sup_hash<9><<<unit_grid(nu, 16), CBLK, 0, s>>>(c, ub, nu, d_sup); break;
-      case 2: k_sup_hash<12><<<unit_grid(nu, 4), CBLK, 0, s>>>(c, ub, nu, d_sup); break;
-      case 3: k_sup_hash<13><<<unit_grid(nu, 1), CBLK, 0, s>>>(c, ub, nu, d_sup); break;
+      case 0: k_sup_lds<6><<<unit_grid(nu, 16), CBLK, 0, s>>>(c, ub, nu, d_sup); break;
+      case 1: k_sup_lds<9><<<unit_grid(nu, 16), CBLK, 0, s>>>(c, ub, nu, d_sup); break;
+      case 2: k_sup_lds<12><<<unit_grid(nu, 4), CBLK, 0, s>>>(c, ub, nu, d_sup); break;
+      case 3: k_sup_lds<13><<<unit_grid(nu, 2), CBLK, 0, s>>>(c, ub, nu, d_sup); break;
       default: k_sup_search<<<unit_grid(nu, 8), CBLK, 0, s>>>(c, ub, nu, d_sup); break;
     }
     GC_LAUNCH_CHECK();

@@ -75,6 +75,11 @@ struct gc_graph {
   gc::CsrStore work[2];     // k-truss ping-pong working CSRs
   gc::UnitStore work_units;
   gc::DeviceBuffer t_sup, t_flag, t_pos, t_misc;  // k-truss round state
+  int strategy[5] = {0, 0, 0, 0, 2};             // count strategy per degree bin
+  // last decomposition: [0] levels with removals, [1] rounds, [2] frontier
+  // edges, [3] largest frontier, [4] compactions, [5..36] rounds by
+  // floor(log2(frontier size))
+  int64_t peel_stats[37] = {0};
   size_t device_bytes() const {
     return u.bytes + v.bytes + rank.bytes + vid.bytes + csr.bytes() + units.units.bytes +
            units_sup.units.bytes + ws.buf.bytes + work[0].bytes() + work[1].bytes() +
@@ -101,7 +106,9 @@ gc_status build_units_support(const CsrView &c, UnitStore &u, Workspace &ws, hip
 gc_status count_triangles(const CsrView &c, const UnitStore &u, unsigned long long *d_count,
                           hipStream_t s);
 constexpr int kCountBins = 5;
-constexpr int kCountStrategies = 3;  // 0 hash (load <= 1/2), 1 hash (load <= 1/4), 2 search
+// 0/1 linear-probing LDS table (load <= 1/2, 1/4), 2 binary search in HBM,
+// 3/4 bucketed LDS table (load <= 1/2, 1/4)
+constexpr int kCountStrategies = 5;
 bool count_strategy_valid(int bin, int strategy);
 // Count with a chosen strategy per bin (strategy may be null = defaults); per
 // graph counts if d_per_graph != null (graph_of_rank maps a rank to its graph).
@@ -112,6 +119,29 @@ gc_status count_bin(const CsrView &c, const UnitStore &u, int bin, int strategy,
                     unsigned long long *d_total, unsigned long long *d_per_graph,
                     const int32_t *graph_of_rank, hipStream_t s);
 gc_status slot_support(const CsrView &c, const UnitStore &u, int32_t *d_sup, hipStream_t s);
+// Time every admissible strategy of every bin that has work (HIP events, the
+// first run of each discarded) and return the fastest per bin in strategy[];
+// ms[bin * kCountStrategies + st] = mean time (-1 if not run).  Counts go to
+// d_total or, per graph, to d_per_graph (graph_of_rank != null).
+gc_status autotune_bins(const CsrView &c, const UnitStore &u, int *strategy, float *ms,
+                        unsigned long long *d_total, unsigned long long *d_per_graph,
+                        const int32_t *graph_of_rank, hipStream_t s);
+// Strategy cache file (environment GC_AUTOTUNE_CACHE): load into / save from
+// strategy[kCountBins] for the given device.
+void load_strategy_cache(int device, int *strategy);
+void save_strategy_cache(int device, const int *strategy);
+
+// One graph of a multi-graph count launch (device-side descriptor).
+struct GraphDesc {
+  CsrView c;
+  const int4 *units;
+  int64_t bin_begin[kCountBins];
+};
+// Count triangles of nh graphs in one launch per bin: d_desc[nh] descriptors,
+// d_pre / h_pre [kCountBins][nh+1] per-bin prefix sums of the graphs' unit
+// counts (device and host copies); per-graph counts into d_out[nh].
+gc_status count_multi_launch(const GraphDesc *d_desc, const int64_t *d_pre, const int64_t *h_pre,
+                             int32_t nh, unsigned long long *d_out, hipStream_t s);
 // (gc_peel.hip) truss numbers by peeling with incremental support updates;
 // tau must hold m entries.
 gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStream_t s);

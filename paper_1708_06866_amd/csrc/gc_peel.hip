@@ -273,6 +273,7 @@ static gc_status compact_peel(gc_graph *g, PeelState &ps, CsrView &c, int &next,
   c = w.view(n, kept);
   next ^= 1;
   ps.cur = o;
+  ++g->peel_stats[4];
   return GC_OK;
 }
 
@@ -317,6 +318,8 @@ gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStre
   int32_t L = m;
   int next_store = 0;
   int32_t kmax = 2;
+  int64_t *stats = g->peel_stats;
+  for (int i = 0; i < 37; ++i) stats[i] = 0;
   const int peel_grid = 256 * 8;
 
   for (;;) {
@@ -355,9 +358,14 @@ gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStre
     GC_HIP(hipMemcpyAsync(&nfront, misc, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     GC_HIP(hipStreamSynchronize(s));
     int64_t dead_since = 0;
+    if (nfront > 0) ++stats[0];
     // ---- rounds of level k ----
     while (nfront > 0) {
       kmax = k - 1 > kmax ? k - 1 : kmax;
+      ++stats[1];
+      stats[2] += nfront;
+      if (nfront > stats[3]) stats[3] = nfront;
+      ++stats[5 + (31 - __builtin_clz((unsigned)nfront))];
       k_set_i32<<<1, 64, 0, s>>>(misc, 0, 0);
       unsigned pg = (unsigned)((nfront + 3) / 4);
       if (pg > (unsigned)peel_grid) pg = peel_grid;

@@ -303,3 +303,30 @@ def test_decomposition_peel_equals_rounds(monkeypatch):
         assert k_rounds == k_peel
         assert np.array_equal(t_rounds, t_peel.cpu().numpy())
         g.free()
+
+
+@pytest.mark.parametrize("strategy", [[0, 0, 0, 0, 2], [1, 1, 1, 1, 2], [2, 2, 2, 2, 2],
+                                      [3, 3, 3, 3, 2], [4, 4, 4, 4, 2]])
+def test_count_strategies_agree(strategy):
+    """Every count strategy gives the oracle's count (bins 0-3 exercised by the
+    R-MAT graph and a complete graph reaching d+ > 2048)."""
+    for src, dst, n in (gg.rmat(14, 16, seed=2), gg.complete(2300)):
+        g = gc.build_graph(src, dst, n)
+        g.set_strategy(strategy)
+        u, v = oracle.normalise(src, dst, n)
+        want = n * (n - 1) * (n - 2) // 6 if len(u) == n * (n - 1) // 2 else \
+            oracle.triangle_count(n, u, v)
+        assert g.triangle_count() == want, strategy
+        g.free()
+
+
+def test_autotune_keeps_counts():
+    src, dst, n = gg.rmat(15, 16, seed=3)
+    g = gc.build_graph(src, dst, n)
+    T = g.triangle_count()
+    st, ms = g.autotune()
+    say("graph autotune", st.tolist(), np.round(ms, 3).tolist())
+    assert st[4] == 2 and g.triangle_count() == T
+    with pytest.raises(gc.GCError):
+        g.set_strategy([0, 0, 0, 0, 1])
+    g.free()
