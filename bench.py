@@ -78,6 +78,30 @@ def algorithmic_bytes(row_ptr: np.ndarray, col: np.ndarray, chunk: int = 128) ->
             "B_model_min": min(16 * n + 20 * m + 4 * s_dst, 16 * n + 24 * m + 4 * s_src)}
 
 
+def profiled_traffic(workload: str, scale: int, ef: int, seed: int, strategy) -> int | None:
+    """HBM bytes per count pass from the committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE, each scaled by a 1 GiB elementwise kernel), if
+    that summary was taken on this workload, with these strategies and with
+    the count kernels' current source; else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "tc_count_rmat_s24.md")
+    src = os.path.join(ROOT, "paper_1708_06866_amd", "csrc", "gc_count.hip")
+    if not (os.path.exists(path) and os.path.exists(src)) or strategy is None:
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("#", "|", " ")):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    try:
+        ok = (kv["count_source_sha256"] == hashlib.sha256(open(src, "rb").read()).hexdigest()
+              and kv["workload"] == "%s %d %d %d" % (workload, scale, ef, seed)
+              and [int(x) for x in kv["strategy"].split()] == list(strategy))
+        return int(kv["traffic_bytes_per_pass"]) if ok else None
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(scale: int, ef: int, seed: int) -> dict:
     """The oracle as it stands, single thread, on R-MAT of `scale` (a bounded
     sample of the same family): normalise + count + decomposition."""
@@ -423,8 +447,12 @@ def main():
         "tc_edges_per_s": m / (tc_ms / 1000.0),
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-            "kernel": "triangle-count pass (k_tc_hash / k_tc_search over all degree bins)",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": profiled_traffic(args.workload, args.scale, args.ef, args.seed,
+                                        tuned["strategy"] if tuned else None),
+            "kernel": "triangle-count pass (k_tc_lds / k_tc_search, one dispatch per degree bin)",
+            "traffic_source": "profiles/tc_count_rmat_s24.md (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                              "calibrated; null unless taken on these kernels and strategies)",
             "algorithmic_bytes": tc_bytes, "probes": ab["probes"],
             "survey_model_bytes": ab["B_model_min"],
         },

@@ -155,9 +155,11 @@ gc_status gc_truss_decomposition(gc_graph *g, int32_t *d_truss, int64_t cap,
                                  gc_stream stream, int32_t *h_kmax);
 
 /* Counters of the last gc_truss_decomposition on this handle (first `cap`
- * of 37, host): [0] levels that removed edges, [1] rounds, [2] edges removed
+ * of 41, host): [0] levels that removed edges, [1] rounds, [2] edges removed
  * over all rounds (= m), [3] largest round, [4] compactions of the edge list,
- * [5 + i] rounds whose removal count r has floor(log2 r) = i. */
+ * [5 + i] rounds whose removal count r has floor(log2 r) = i, [37]
+ * candidate third vertices examined, [38] of them searched (edge alive),
+ * [39] triangles found, [40] triangles destroyed (each exactly once). */
 gc_status gc_graph_truss_stats(const gc_graph *g, int64_t *h_stats, int32_t cap);
 
 /* ------------------------------------------------------------------------ */

@@ -222,12 +222,14 @@ class Graph:
     def truss_stats(self) -> dict:
         """Counters of the last truss decomposition on this handle."""
         import numpy as np
-        v = np.zeros(37, dtype=np.int64)
-        _check(lib().gc_graph_truss_stats(self.handle, ctypes.c_void_p(v.ctypes.data), 37),
+        v = np.zeros(41, dtype=np.int64)
+        _check(lib().gc_graph_truss_stats(self.handle, ctypes.c_void_p(v.ctypes.data), 41),
                "gc_graph_truss_stats")
         return {"levels": int(v[0]), "rounds": int(v[1]), "removed": int(v[2]),
                 "largest_round": int(v[3]), "compactions": int(v[4]),
-                "rounds_by_log2_size": [int(x) for x in v[5:]]}
+                "rounds_by_log2_size": [int(x) for x in v[5:37]],
+                "candidates": int(v[37]), "searches": int(v[38]),
+                "triangles_found": int(v[39]), "triangles_destroyed": int(v[40])}
 
     def set_strategy(self, strategy):
         import numpy as np

@@ -91,12 +91,15 @@ inline unsigned grid_for(int64_t work, int per_block, int64_t cap = 1 << 20) {
 // Scans and sort (gc_scan.hip, gc_sort.hip)
 // --------------------------------------------------------------------------
 
-// Scratch needed by exclusive_scan for n elements.
+// Scratch needed by exclusive_scan or exclusive_scan64 for n elements.
 size_t scan_scratch_bytes(int64_t n);
 // out[i] = sum_{j<i} in[i] for i < n, and out[n] = total (out holds n+1).
 // In-place (out == in) is allowed.  n < 2^31, total < 2^31.
 gc_status exclusive_scan(const int32_t *in, int32_t *out, int64_t n,
                          void *scratch, hipStream_t s);
+// The same with 64-bit sums: out (n+1 entries) may total beyond 2^31.
+gc_status exclusive_scan64(const int32_t *in, int64_t *out, int64_t n,
+                           void *scratch, hipStream_t s);
 
 // Scratch needed by radix_sort for n keys.
 size_t sort_scratch_bytes(int64_t n);

@@ -473,7 +473,9 @@ gc_status autotune_bins(const CsrView &c, const UnitStore &u, int *strategy, flo
       }
       if (st != GC_OK) break;
       ms[bin * kCountStrategies + k] = acc / 2;
-      if (best < 0 || acc / 2 < best) {
+      // a later strategy must win by 3% to replace an earlier one (stable
+      // choices when two are within timing noise)
+      if (best < 0 || acc / 2 < 0.97f * best) {
         best = acc / 2;
         strategy[bin] = k;
       }

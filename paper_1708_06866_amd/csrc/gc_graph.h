@@ -10,7 +10,8 @@ namespace gc {
 // vertex" schedule walks.  For oriented slot p (edge r -> col[p], r = src[p]):
 //   tail(p) = [p + 1, row_ptr[r + 1])   the part of N+(r) above col[p]
 // and the in-list of vertex x lists, for every slot p with col[p] = x, the
-// range tail(p) packed as int2 {p + 1, row_end}; in_slot[j] is p itself.
+// range tail(p) packed as int2 {p + 1, row_end}; in_slot[j] is p itself and
+// in_src[j] its source (in-lists are sorted by source).
 struct CsrView {
   int32_t n = 0;
   int32_t m = 0;
@@ -21,12 +22,13 @@ struct CsrView {
   const int32_t *in_ptr = nullptr;   // [n+1]
   const int2 *in_tail = nullptr;     // [m]
   const int32_t *in_slot = nullptr;  // [m]
+  const int32_t *in_src = nullptr;   // [m]
 };
 
 // Owned device arrays of one oriented CSR (base graph or a k-truss working
 // copy).
 struct CsrStore {
-  DeviceBuffer row_ptr, col, src, eid, in_ptr, in_tail, in_slot;
+  DeviceBuffer row_ptr, col, src, eid, in_ptr, in_tail, in_slot, in_src;
   CsrView view(int32_t n, int32_t m) const {
     CsrView v;
     v.n = n;
@@ -38,15 +40,16 @@ struct CsrStore {
     v.in_ptr = static_cast<const int32_t *>(in_ptr.ptr);
     v.in_tail = static_cast<const int2 *>(in_tail.ptr);
     v.in_slot = static_cast<const int32_t *>(in_slot.ptr);
+    v.in_src = static_cast<const int32_t *>(in_src.ptr);
     return v;
   }
   void release() {
     dfree(row_ptr); dfree(col); dfree(src); dfree(eid);
-    dfree(in_ptr); dfree(in_tail); dfree(in_slot);
+    dfree(in_ptr); dfree(in_tail); dfree(in_slot); dfree(in_src);
   }
   size_t bytes() const {
     return row_ptr.bytes + col.bytes + src.bytes + eid.bytes + in_ptr.bytes +
-           in_tail.bytes + in_slot.bytes;
+           in_tail.bytes + in_slot.bytes + in_src.bytes;
   }
 };
 
@@ -78,8 +81,9 @@ struct gc_graph {
   int strategy[5] = {0, 0, 0, 0, 2};             // count strategy per degree bin
   // last decomposition: [0] levels with removals, [1] rounds, [2] frontier
   // edges, [3] largest frontier, [4] compactions, [5..36] rounds by
-  // floor(log2(frontier size))
-  int64_t peel_stats[37] = {0};
+  // floor(log2(frontier size)), [37] candidates examined, [38] searched,
+  // [39] triangles found, [40] triangles destroyed (subtracted)
+  int64_t peel_stats[41] = {0};
   size_t device_bytes() const {
     return u.bytes + v.bytes + rank.bytes + vid.bytes + csr.bytes() + units.units.bytes +
            units_sup.units.bytes + ws.buf.bytes + work[0].bytes() + work[1].bytes() +

@@ -26,6 +26,8 @@
 //
 // Results equal the rounds of Alg. 4 (bulk removal per round, same frontier
 // sets); only the work per round differs.
+#include <cstdlib>
+
 #include "gc_graph.h"
 
 namespace gc {
@@ -47,16 +49,16 @@ __device__ __forceinline__ int32_t find_col(const int32_t *__restrict__ col, int
 // Triangle {p, q1, q2} seen from frontier edge p (q2 < 0: no triangle).  Every
 // active lane of the wave calls this together, so the next-frontier appends
 // are aggregated per wave.
-__device__ __forceinline__ void destroy(bool found, int32_t p, int32_t q1, int32_t q2,
+__device__ __forceinline__ bool destroy(bool found, int32_t p, int32_t q1, int32_t q2,
                                         int32_t thr, const uint8_t *__restrict__ state,
                                         int32_t *__restrict__ sup, int32_t *__restrict__ next,
                                         int32_t *__restrict__ next_count) {
-  bool t1 = false, t2 = false;
+  bool t1 = false, t2 = false, ours = false;
   if (found) {
     const uint8_t s1 = state[q1], s2 = state[q2];
     // skip if destroyed in an earlier round, or owned by a smaller frontier edge
-    const bool ours = s1 != EDGE_DEAD && s2 != EDGE_DEAD &&
-                      !(s1 == EDGE_FRONT && q1 < p) && !(s2 == EDGE_FRONT && q2 < p);
+    ours = s1 != EDGE_DEAD && s2 != EDGE_DEAD &&
+           !(s1 == EDGE_FRONT && q1 < p) && !(s2 == EDGE_FRONT && q2 < p);
     if (ours) {
       if (s1 == EDGE_ALIVE) t1 = atomicSub(&sup[q1], 1) == thr;
       if (s2 == EDGE_ALIVE) t2 = atomicSub(&sup[q2], 1) == thr;
@@ -66,43 +68,345 @@ __device__ __forceinline__ void destroy(bool found, int32_t p, int32_t q1, int32
   if (t1) next[at] = q1;
   at = wave_append(t2, next_count);
   if (t2) next[at] = q2;
+  return ours;
 }
 
+constexpr int PEEL_U = 4;  // candidates per lane in flight
+
+// Searches of PEEL_U keys, each in its own sorted range arr[u][lo, hi), run in
+// lockstep so their loads overlap; out[u] = index of key[u] or -1 (also -1
+// where the range is empty).
+__device__ __forceinline__ void find_many(const int32_t *const (&arr)[PEEL_U],
+                                          const int32_t (&lo)[PEEL_U], const int32_t (&hi)[PEEL_U],
+                                          const int32_t (&key)[PEEL_U], int32_t (&out)[PEEL_U]) {
+  int32_t l[PEEL_U], n[PEEL_U];
+#pragma unroll
+  for (int u = 0; u < PEEL_U; ++u) { l[u] = lo[u]; n[u] = hi[u] - lo[u]; }
+  for (;;) {
+    bool any = false;
+    int32_t v[PEEL_U];
+#pragma unroll
+    for (int u = 0; u < PEEL_U; ++u) v[u] = n[u] > 0 ? arr[u][l[u] + (n[u] >> 1)] : 0;
+#pragma unroll
+    for (int u = 0; u < PEEL_U; ++u) {
+      if (n[u] > 0) {
+        const int32_t half = n[u] >> 1;
+        if (v[u] < key[u]) { l[u] += half + 1; n[u] -= half + 1; } else { n[u] = half; }
+        any |= n[u] > 0;
+      }
+    }
+    if (!any) break;
+  }
+#pragma unroll
+  for (int u = 0; u < PEEL_U; ++u) out[u] = (l[u] < hi[u] && arr[u][l[u]] == key[u]) ? l[u] : -1;
+}
+
+__device__ __forceinline__ int32_t lower_bound_i32(const int32_t *__restrict__ a, int32_t lo,
+                                                   int32_t hi, int32_t key) {
+  while (lo < hi) {
+    const int32_t mid = lo + ((hi - lo) >> 1);
+    if (a[mid] < key) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// The lists around frontier edge p = (a -> b): rows and in-lists of a and b,
+// and the position of a in b's in-list.
+struct PeelEdge {
+  int32_t ra0, ra1, rb0, rb1, ia0, ia1, ib0, ib1, ibA;
+};
+
+__device__ __forceinline__ PeelEdge peel_edge(const CsrView &c, int32_t a, int32_t b) {
+  PeelEdge e;
+  e.ra0 = c.row_ptr[a]; e.ra1 = c.row_ptr[a + 1];
+  e.rb0 = c.row_ptr[b]; e.rb1 = c.row_ptr[b + 1];
+  e.ia0 = c.in_ptr[a]; e.ia1 = c.in_ptr[a + 1];
+  e.ib0 = c.in_ptr[b]; e.ib1 = c.in_ptr[b + 1];
+  e.ibA = lower_bound_i32(c.in_src, e.ib0, e.ib1, a);  // in_src[ibA] == a (edge p)
+  return e;
+}
+
+// One of the three intersections (see k_peel): iterate A[A0, A0 + nA), search
+// B[B0, B0 + nB); nA = 0 when either side is empty.  flags: bit 0 A is an
+// in-list, bit 1 B is an in-list, bit 2 A holds the edge between a and x.
+struct PeelCase {
+  int32_t A0, nA, B0, nB;
+  uint32_t flags;
+};
+
+__device__ __forceinline__ PeelCase peel_case(const PeelEdge &e, int32_t p, int cs) {
+  int32_t A0, A1, B0, B1;
+  bool A_in, B_in;  // side is an in-list (keys in_src, slots in_slot) or a row
+  if (cs == 0) { A0 = p + 1; A1 = e.ra1; A_in = false; B0 = e.rb0; B1 = e.rb1; B_in = false; }
+  else if (cs == 1) { A0 = e.ra0; A1 = p; A_in = false; B0 = e.ibA + 1; B1 = e.ib1; B_in = true; }
+  else { A0 = e.ia0; A1 = e.ia1; A_in = true; B0 = e.ib0; B1 = e.ibA; B_in = true; }
+  bool a_is_ax = cs != 2;
+  if (A1 - A0 > B1 - B0) {  // iterate the shorter side
+    int32_t t;
+    t = A0; A0 = B0; B0 = t;
+    t = A1; A1 = B1; B1 = t;
+    const bool tb = A_in; A_in = B_in; B_in = tb;
+    a_is_ax = !a_is_ax;
+  }
+  PeelCase pc;
+  pc.A0 = A0;
+  pc.B0 = B0;
+  pc.nB = B1 - B0;
+  pc.nA = (A1 - A0 > 0 && B1 - B0 > 0) ? A1 - A0 : 0;
+  pc.flags = (A_in ? 1u : 0u) | (B_in ? 2u : 0u) | (a_is_ax ? 4u : 0u);
+  return pc;
+}
+
+// One round of level k.  `wpe` waves share each frontier edge p = (a -> b).
+// Its triangles {a, b, x} split by the rank of x, and each case intersects two
+// sorted lists, iterating the shorter (A) and searching the longer (B):
+//   x > b      tail of a's row after p (a -> x)   vs  b's row (b -> x)
+//   a < x < b  head of a's row before p (a -> x)  vs  b's in-list, sources in (a, b)
+//   x < a      a's in-list (x -> a)               vs  b's in-list, sources < a
+// Each lane takes PEEL_U candidates of A per step (stride 64 * wpe), searched
+// in lockstep.
+// `work` (optional) holds 4 counters per wave: candidates, searches,
+// triangles found, triangles destroyed.
 __global__ __launch_bounds__(PBLK) void k_peel(CsrView c, const int32_t *__restrict__ front,
-                                               int32_t nfront, int32_t thr,
+                                               int32_t nfront, int32_t thr, int32_t wpe,
                                                int32_t *__restrict__ sup,
                                                const uint8_t *__restrict__ state,
                                                int32_t *__restrict__ next,
-                                               int32_t *__restrict__ next_count) {
+                                               int32_t *__restrict__ next_count,
+                                               unsigned long long *__restrict__ work) {
   const int lane = threadIdx.x & 63;
-  const int64_t wid = ((int64_t)blockIdx.x * PBLK + threadIdx.x) >> 6;
+  int32_t n_cand = 0, n_search = 0, n_found = 0, n_ours = 0;  // per-lane work counters
+  const int64_t gw = ((int64_t)blockIdx.x * PBLK + threadIdx.x) >> 6;
   const int64_t nw = ((int64_t)gridDim.x * PBLK) >> 6;
-  for (int64_t f = wid; f < nfront; f += nw) {
+  const int64_t groups = nw / wpe;
+  const int32_t sub = (int32_t)(gw % wpe);
+  const int32_t stride = 64 * wpe;
+  for (int64_t f = gw / wpe; f < nfront && gw < groups * wpe; f += groups) {
     const int32_t p = front[f];
     const int32_t a = c.src[p], b = c.col[p];
-    const int32_t rb0 = c.row_ptr[b], rb1 = c.row_ptr[b + 1];
-    // third vertex from the out-row of a
-    const int32_t ra1 = c.row_ptr[a + 1];
-    for (int32_t i = c.row_ptr[a] + lane; i < ra1; i += 64) {
-      int32_t q2 = -1;
-      if (i != p && state[i] != EDGE_DEAD) {
-        const int32_t x = c.col[i];
-        q2 = x > b ? find_col(c.col, rb0, rb1, x)
-                   : find_col(c.col, c.row_ptr[x], c.row_ptr[x + 1], b);
+    const PeelEdge e = peel_edge(c, a, b);
+#pragma unroll 1
+    for (int cs = 0; cs < 3; ++cs) {
+      const PeelCase pc = peel_case(e, p, cs);
+      const int32_t nA = pc.nA, A0 = pc.A0, B0 = pc.B0, B1 = pc.B0 + pc.nB;
+      if (nA == 0) continue;
+      const bool A_in = pc.flags & 1u, B_in = pc.flags & 2u, a_is_ax = pc.flags & 4u;
+      const int32_t *keysB = B_in ? c.in_src : c.col;
+      for (int32_t t0 = sub * 64 + lane; t0 - lane < nA; t0 += stride * PEEL_U) {
+        int32_t qk[PEEL_U], key[PEEL_U], lo[PEEL_U], hi[PEEL_U], idx[PEEL_U];
+#pragma unroll
+        for (int u = 0; u < PEEL_U; ++u) {
+          const int32_t t = t0 + u * stride;
+          qk[u] = -1;
+          key[u] = 0;
+          lo[u] = 0;
+          hi[u] = 0;
+          if (t < nA) {
+            ++n_cand;
+            const int32_t i = A0 + t;
+            const int32_t q = A_in ? c.in_slot[i] : i;
+            if (state[q] != EDGE_DEAD) {
+              qk[u] = q;
+              key[u] = A_in ? c.in_src[i] : c.col[i];
+              lo[u] = B0;
+              hi[u] = B1;
+              ++n_search;
+            }
+          }
+        }
+        const int32_t *arr[PEEL_U] = {keysB, keysB, keysB, keysB};
+        find_many(arr, lo, hi, key, idx);
+#pragma unroll
+        for (int u = 0; u < PEEL_U; ++u) {
+          int32_t q1 = -1, q2 = -1;
+          if (qk[u] >= 0 && idx[u] >= 0) {
+            const int32_t other = B_in ? c.in_slot[idx[u]] : idx[u];
+            q1 = a_is_ax ? qk[u] : other;  // edge between a and x
+            q2 = a_is_ax ? other : qk[u];  // edge between b and x
+          }
+          const bool fnd = q1 >= 0;
+          n_found += fnd;
+          n_ours += destroy(fnd, p, q1, q2, thr, state, sup, next, next_count);
+        }
       }
-      destroy(q2 >= 0, p, i, q2, thr, state, sup, next, next_count);
     }
-    // third vertex below a: from the in-list of a
-    const int32_t ia1 = c.in_ptr[a + 1];
-    for (int32_t j = c.in_ptr[a] + lane; j < ia1; j += 64) {
-      const int32_t q1 = c.in_slot[j];
-      int32_t q2 = -1;
-      if (state[q1] != EDGE_DEAD) {
-        const int32_t x = c.src[q1];
-        q2 = find_col(c.col, c.row_ptr[x], c.row_ptr[x + 1], b);
+  }
+  if (work) {
+    const int32_t a0 = wave_sum_i32(n_cand), a1 = wave_sum_i32(n_search);
+    const int32_t a2 = wave_sum_i32(n_found), a3 = wave_sum_i32(n_ours);
+    if (lane == 0) {  // this wave's own slots: no other wave writes them
+      work[gw * 4 + 0] += (unsigned long long)a0;
+      work[gw * 4 + 1] += (unsigned long long)a1;
+      work[gw * 4 + 2] += (unsigned long long)a2;
+      work[gw * 4 + 3] += (unsigned long long)a3;
+    }
+  }
+}
+
+// ---- load-balanced round: every lane takes one candidate ----
+//
+// For frontiers of many edges, most edges have short lists and a wave per edge
+// leaves most lanes idle.  The plan kernel writes each edge's three cases and
+// its candidate count (at least 1, so that every edge owns a candidate index);
+// an exclusive scan of the counts numbers all candidates of the round; the
+// flat kernel splits that range evenly over its blocks, and each lane finds
+// the edge of its candidate by binary search in the block's slice of the scan.
+// Per edge the plan holds 4 int4: {p, c1, c2, flags}, where case 1 starts at
+// candidate c1 and case 2 at c2, then {A0, nA, B0, nB} of cases 0, 1, 2.
+
+constexpr int FLAT_TILE = PBLK * PEEL_U;  // candidates per block step
+constexpr int FLAT_BLOCKS = 2048;         // 8 blocks (32 waves) per CU
+
+__global__ __launch_bounds__(PBLK) void k_peel_plan(CsrView c, const int32_t *__restrict__ front,
+                                                    int32_t nfront, int4 *__restrict__ plan,
+                                                    int32_t *__restrict__ cnt) {
+  for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < nfront;
+       f += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t p = front[f];
+    const PeelEdge e = peel_edge(c, c.src[p], c.col[p]);
+    int32_t tot = 0, cum[2] = {0, 0};
+    uint32_t flags = 0;
+#pragma unroll
+    for (int cs = 0; cs < 3; ++cs) {
+      const PeelCase pc = peel_case(e, p, cs);
+      plan[4 * f + 1 + cs] = make_int4(pc.A0, pc.nA, pc.B0, pc.nB);
+      flags |= pc.flags << (3 * cs);
+      tot += pc.nA;
+      if (cs < 2) cum[cs] = tot;
+    }
+    plan[4 * f] = make_int4(p, cum[0], cum[1], (int32_t)flags);
+    cnt[f] = tot > 0 ? tot : 1;
+  }
+}
+
+// First index i of a[0, n) with a[i] > x (a sorted).
+template <class T>
+__device__ __forceinline__ int32_t upper_bound_t(const T *a, int32_t n, int64_t x) {
+  int32_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int32_t mid = lo + ((hi - lo) >> 1);
+    if ((int64_t)a[mid] <= x) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// offs[0, nfront] is the exclusive scan of the plan's counts; offs[nfront] is
+// the round's candidate total, read here so the host need not know it.
+__global__ __launch_bounds__(PBLK) void k_peel_flat(CsrView c, const int4 *__restrict__ plan,
+                                                    const int64_t *__restrict__ offs,
+                                                    int32_t nfront, int32_t thr,
+                                                    int32_t *__restrict__ sup,
+                                                    const uint8_t *__restrict__ state,
+                                                    int32_t *__restrict__ next,
+                                                    int32_t *__restrict__ next_count,
+                                                    unsigned long long *__restrict__ work) {
+  // The block's slice of offs, relative to the step's first candidate t0 and
+  // clamped to int32: a candidate's position in its edge and every index
+  // derived from it then stay 32-bit values well inside range, although the
+  // round's total (and so t0) may exceed 2^31.
+  __shared__ int32_t s_rel[FLAT_TILE + 1];
+  __shared__ int32_t s_f;
+  const int tid = threadIdx.x, lane = tid & 63;
+  int32_t n_cand = 0, n_search = 0, n_found = 0, n_ours = 0;
+  const int64_t total = offs[nfront];
+  int64_t chunk = (total + gridDim.x - 1) / gridDim.x;
+  chunk = (chunk + FLAT_TILE - 1) / FLAT_TILE * FLAT_TILE;
+  const int64_t lo = (int64_t)blockIdx.x * chunk;
+  const int64_t hi = lo + chunk < total ? lo + chunk : total;
+  if (lo < hi) {  // the same for the whole block
+    if (tid == 0) s_f = upper_bound_t(offs, nfront + 1, lo) - 1;
+    __syncthreads();
+    for (int64_t t0 = lo; t0 < hi; t0 += FLAT_TILE) {
+      // edges [fc, fc + nv - 1) hold every candidate of this step: each edge
+      // has at least one, and edge fc holds t0 (so s_rel[0] is in (-2^31, 0])
+      const int32_t fc = s_f;
+      const int32_t nv = nfront + 1 - fc < FLAT_TILE + 1 ? nfront + 1 - fc : FLAT_TILE + 1;
+      const int32_t lim = hi - t0 < FLAT_TILE ? (int32_t)(hi - t0) : FLAT_TILE;
+      for (int i = tid; i < nv; i += PBLK) {
+        const int64_t d = offs[fc + i] - t0;
+        s_rel[i] = d < (int64_t)INT32_MAX ? (int32_t)d : INT32_MAX;
       }
-      destroy(q2 >= 0, p, q1, q2, thr, state, sup, next, next_count);
+      __syncthreads();
+      int32_t pk[PEEL_U], qk[PEEL_U], key[PEEL_U], blo[PEEL_U], bhi[PEEL_U], idx[PEEL_U];
+      uint32_t fl[PEEL_U];
+      const int32_t *arr[PEEL_U];
+#pragma unroll
+      for (int u = 0; u < PEEL_U; ++u) {
+        const int32_t loc = u * PBLK + tid;  // candidate t0 + loc
+        pk[u] = -1;
+        qk[u] = -1;
+        key[u] = 0;
+        blo[u] = 0;
+        bhi[u] = 0;
+        fl[u] = 0;
+        arr[u] = c.col;
+        if (loc < lim) {
+          const int32_t j = upper_bound_t(s_rel, nv, loc) - 1;
+          const int64_t f = (int64_t)fc + j;
+          int32_t r = loc - s_rel[j];  // position within edge f's candidates
+          const int4 h = plan[4 * f];
+          const int cs = r < h.y ? 0 : (r < h.z ? 1 : 2);
+          r -= cs == 0 ? 0 : (cs == 1 ? h.y : h.z);
+          const int4 pc = plan[4 * f + 1 + cs];
+          if (r < pc.y) {  // not the placeholder of an edge without candidates
+            ++n_cand;
+            const uint32_t flags = ((uint32_t)h.w >> (3 * cs)) & 7u;
+            const int32_t i = pc.x + r;
+            const int32_t q = (flags & 1u) ? c.in_slot[i] : i;
+            if (state[q] != EDGE_DEAD) {
+              ++n_search;
+              pk[u] = h.x;
+              qk[u] = q;
+              fl[u] = flags;
+              key[u] = (flags & 1u) ? c.in_src[i] : c.col[i];
+              blo[u] = pc.z;
+              bhi[u] = pc.z + pc.w;
+              arr[u] = (flags & 2u) ? c.in_src : c.col;
+            }
+          }
+        }
+      }
+      find_many(arr, blo, bhi, key, idx);
+#pragma unroll
+      for (int u = 0; u < PEEL_U; ++u) {
+        int32_t q1 = -1, q2 = -1;
+        if (qk[u] >= 0 && idx[u] >= 0) {
+          const int32_t other = (fl[u] & 2u) ? c.in_slot[idx[u]] : idx[u];
+          const bool a_is_ax = fl[u] & 4u;
+          q1 = a_is_ax ? qk[u] : other;  // edge between a and x
+          q2 = a_is_ax ? other : qk[u];  // edge between b and x
+        }
+        const bool fnd = q1 >= 0;
+        n_found += fnd;
+        n_ours += destroy(fnd, pk[u], q1, q2, thr, state, sup, next, next_count);
+      }
+      __syncthreads();  // s_rel and s_f read by every lane
+      if (tid == 0 && t0 + FLAT_TILE < hi) s_f = fc + upper_bound_t(s_rel, nv, (int64_t)FLAT_TILE) - 1;
+      __syncthreads();
     }
+  }
+  if (work) {
+    const int64_t gw = ((int64_t)blockIdx.x * PBLK + tid) >> 6;
+    const int32_t a0 = wave_sum_i32(n_cand), a1 = wave_sum_i32(n_search);
+    const int32_t a2 = wave_sum_i32(n_found), a3 = wave_sum_i32(n_ours);
+    if (lane == 0) {  // this wave's own slots
+      work[gw * 4 + 0] += (unsigned long long)a0;
+      work[gw * 4 + 1] += (unsigned long long)a1;
+      work[gw * 4 + 2] += (unsigned long long)a2;
+      work[gw * 4 + 3] += (unsigned long long)a3;
+    }
+  }
+}
+
+__global__ void k_sum_work(const unsigned long long *__restrict__ w, int64_t nw,
+                           unsigned long long *__restrict__ out) {
+  unsigned long long acc[4] = {0, 0, 0, 0};
+  for (int64_t i = threadIdx.x; i < nw; i += blockDim.x)
+    for (int k = 0; k < 4; ++k) acc[k] += w[i * 4 + k];
+  for (int k = 0; k < 4; ++k) {
+    unsigned long long v = acc[k];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) atomicAdd(&out[k], v);
   }
 }
 
@@ -158,19 +462,23 @@ __global__ void k_compact_list(const int32_t *__restrict__ list, int32_t L,
   }
 }
 
-__global__ void k_collect(const int32_t *__restrict__ list, int32_t L, int32_t thr,
-                          const int32_t *__restrict__ sup, uint8_t *__restrict__ state,
-                          int32_t *__restrict__ front, int32_t *__restrict__ count) {
+__global__ void k_collect_flags(const int32_t *__restrict__ list, int32_t L, int32_t thr,
+                                const int32_t *__restrict__ sup, int32_t *__restrict__ flag) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < L;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t p = list[i];
-    const bool take = sup[p] < thr;
-    const int32_t at = wave_append(take, count);
-    if (take) {
+       i += (int64_t)gridDim.x * blockDim.x)
+    flag[i] = sup[list[i]] < thr ? 1 : 0;
+}
+
+__global__ void k_collect_scatter(const int32_t *__restrict__ list, int32_t L,
+                                  const int32_t *__restrict__ flag, const int32_t *__restrict__ pos,
+                                  uint8_t *__restrict__ state, int32_t *__restrict__ front) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < L;
+       i += (int64_t)gridDim.x * blockDim.x)
+    if (flag[i]) {
+      const int32_t p = list[i];
       state[p] = EDGE_FRONT;
-      front[at] = p;
+      front[pos[i]] = p;
     }
-  }
 }
 
 __global__ void k_iota(int32_t *__restrict__ x, int32_t n) {
@@ -225,13 +533,13 @@ __global__ void k_rows2(const int32_t *__restrict__ row_ptr, const int32_t *__re
 static unsigned gsz(int64_t work) { return grid_for(work, 256, 65536); }
 
 struct PeelState {
-  DeviceBuffer sup[2], state[2], list[2], front[2], flag, pos, misc;
+  DeviceBuffer sup[2], state[2], list[2], front[2], flag, pos, misc, work, plan, offs;
   int cur = 0;  // which sup/state buffer is live
   ~PeelState() {
     for (int i = 0; i < 2; ++i) {
       dfree(sup[i]); dfree(state[i]); dfree(list[i]); dfree(front[i]);
     }
-    dfree(flag); dfree(pos); dfree(misc);
+    dfree(flag); dfree(pos); dfree(misc); dfree(work); dfree(plan); dfree(offs);
   }
 };
 
@@ -318,9 +626,17 @@ gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStre
   int32_t L = m;
   int next_store = 0;
   int32_t kmax = 2;
+  const int64_t peel_waves = 256 * 32;  // 32 waves per CU
+  static_assert(FLAT_BLOCKS * (PBLK / 64) <= 256 * 32, "work counters sized for peel_waves");
+  // frontiers of at least this many edges take the load-balanced kernel
+  int64_t flat_min = 65536;
+  if (const char *env = std::getenv("GC_PEEL_FLAT_MIN")) flat_min = std::atoll(env);
   int64_t *stats = g->peel_stats;
-  for (int i = 0; i < 37; ++i) stats[i] = 0;
-  const int peel_grid = 256 * 8;
+  for (int i = 0; i < 41; ++i) stats[i] = 0;
+  // per-wave work counters (candidates, searches, triangles), summed at the end
+  GC_TRY(dalloc(ps.work, sizeof(unsigned long long) * 4 * (size_t)peel_waves + 64));
+  unsigned long long *work = static_cast<unsigned long long *>(ps.work.ptr);
+  GC_HIP(hipMemsetAsync(work, 0, sizeof(unsigned long long) * (4 * (size_t)peel_waves + 8), s));
 
   for (;;) {
     int32_t *sup = static_cast<int32_t *>(ps.sup[ps.cur].ptr);
@@ -352,10 +668,14 @@ gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStre
       GC_LAUNCH_CHECK();
       L = c.m;
     }
-    k_collect<<<gsz(L), 256, 0, s>>>(list, L, thr, sup, state, front, misc);
+    k_collect_flags<<<gsz(L), 256, 0, s>>>(list, L, thr, sup, flag);
+    GC_LAUNCH_CHECK();
+    GC_TRY(g->ws.reserve(scan_scratch_bytes((int64_t)L + 1)));
+    GC_TRY(exclusive_scan(flag, pos, L, g->ws.take<char>(scan_scratch_bytes((int64_t)L + 1)), s));
+    k_collect_scatter<<<gsz(L), 256, 0, s>>>(list, L, flag, pos, state, front);
     GC_LAUNCH_CHECK();
     int32_t nfront = 0;
-    GC_HIP(hipMemcpyAsync(&nfront, misc, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    GC_HIP(hipMemcpyAsync(&nfront, pos + L, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     GC_HIP(hipStreamSynchronize(s));
     int64_t dead_since = 0;
     if (nfront > 0) ++stats[0];
@@ -367,10 +687,31 @@ gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStre
       if (nfront > stats[3]) stats[3] = nfront;
       ++stats[5 + (31 - __builtin_clz((unsigned)nfront))];
       k_set_i32<<<1, 64, 0, s>>>(misc, 0, 0);
-      unsigned pg = (unsigned)((nfront + 3) / 4);
-      if (pg > (unsigned)peel_grid) pg = peel_grid;
-      k_peel<<<pg, PBLK, 0, s>>>(c, front, nfront, thr, sup, state, next, misc);
-      GC_LAUNCH_CHECK();
+      if (nfront >= flat_min) {
+        // load-balanced over candidates
+        GC_TRY(dalloc(ps.plan, sizeof(int4) * 4 * (size_t)nfront));
+        GC_TRY(dalloc(ps.offs, sizeof(int64_t) * ((size_t)nfront + 1)));
+        int4 *plan = static_cast<int4 *>(ps.plan.ptr);
+        int64_t *offs = static_cast<int64_t *>(ps.offs.ptr);
+        k_peel_plan<<<gsz(nfront), PBLK, 0, s>>>(c, front, nfront, plan, flag);
+        GC_LAUNCH_CHECK();
+        GC_TRY(g->ws.reserve(scan_scratch_bytes((int64_t)nfront + 1)));
+        GC_TRY(exclusive_scan64(flag, offs, nfront,
+                                g->ws.take<char>(scan_scratch_bytes((int64_t)nfront + 1)), s));
+        k_peel_flat<<<FLAT_BLOCKS, PBLK, 0, s>>>(c, plan, offs, nfront, thr, sup, state, next,
+                                                 misc, work);
+        GC_LAUNCH_CHECK();
+      } else {
+        // keep about peel_waves waves busy: share small frontiers' edges
+        // among several waves each
+        int32_t wpe = 1;
+        while (wpe < 16 && (int64_t)nfront * wpe * 2 <= peel_waves) wpe *= 2;
+        int64_t waves = (int64_t)nfront * wpe;
+        if (waves > peel_waves) waves = peel_waves;
+        const unsigned pg = (unsigned)((waves + (PBLK / 64) - 1) / (PBLK / 64));
+        k_peel<<<pg, PBLK, 0, s>>>(c, front, nfront, thr, wpe, sup, state, next, misc, work);
+        GC_LAUNCH_CHECK();
+      }
       k_advance<<<gsz(nfront), 256, 0, s>>>(front, nfront, next, misc, state, c.eid, tau, k - 1);
       GC_LAUNCH_CHECK();
       int32_t nn = 0;
@@ -390,7 +731,13 @@ gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStre
       }
     }
   }
+  unsigned long long *wsum = work + 4 * (size_t)peel_waves;
+  k_sum_work<<<1, 256, 0, s>>>(work, peel_waves, wsum);
+  GC_LAUNCH_CHECK();
+  unsigned long long hw[4] = {0, 0, 0, 0};
+  GC_HIP(hipMemcpyAsync(hw, wsum, sizeof(hw), hipMemcpyDeviceToHost, s));
   GC_HIP(hipStreamSynchronize(s));
+  for (int i = 0; i < 4; ++i) stats[37 + i] = (int64_t)hw[i];
   if (h_kmax) *h_kmax = kmax;
   return GC_OK;
 }

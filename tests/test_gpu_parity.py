@@ -299,9 +299,16 @@ def test_decomposition_peel_equals_rounds(monkeypatch):
         t_rounds, k_rounds = g.truss_decomposition()
         t_rounds = t_rounds.cpu().numpy()
         monkeypatch.setenv("GC_TRUSS_METHOD", "peel")
-        t_peel, k_peel = g.truss_decomposition()
-        assert k_rounds == k_peel
-        assert np.array_equal(t_rounds, t_peel.cpu().numpy())
+        # every round by the wave-per-edge kernel, every round load-balanced,
+        # and the default split between them
+        for flat_min in ("1000000000", "1", None):
+            if flat_min is None:
+                monkeypatch.delenv("GC_PEEL_FLAT_MIN", raising=False)
+            else:
+                monkeypatch.setenv("GC_PEEL_FLAT_MIN", flat_min)
+            t_peel, k_peel = g.truss_decomposition()
+            assert k_rounds == k_peel, flat_min
+            assert np.array_equal(t_rounds, t_peel.cpu().numpy()), flat_min
         g.free()
 
 
@@ -329,4 +336,23 @@ def test_autotune_keeps_counts():
     assert st[4] == 2 and g.triangle_count() == T
     with pytest.raises(gc.GCError):
         g.set_strategy([0, 0, 0, 0, 1])
+    g.free()
+
+
+@pytest.mark.parametrize("label", ["rmat16", "er16", "K300", "king64"])
+def test_peeling_destroys_each_triangle_once(label, monkeypatch):
+    """Incremental peeling subtracts every triangle exactly once over the whole
+    decomposition, and removes every edge exactly once."""
+    src, dst, n = {"rmat16": gg.rmat(16, 16, seed=4), "er16": gg.er(1 << 16, 16 << 16, seed=4),
+                   "K300": gg.complete(300), "king64": gg.king(64)}[label]
+    g = gc.build_graph(src, dst, n)
+    T = g.triangle_count()
+    for flat_min in ("1000000000", "1"):
+        monkeypatch.setenv("GC_PEEL_FLAT_MIN", flat_min)
+        g.truss_decomposition()
+        st = g.truss_stats()
+        say(label, flat_min, {k: v for k, v in st.items() if k != "rounds_by_log2_size"})
+        assert st["triangles_destroyed"] == T
+        assert st["removed"] == g.m
+        assert sum(st["rounds_by_log2_size"]) == st["rounds"]
     g.free()
