@@ -159,7 +159,10 @@ gc_status gc_truss_decomposition(gc_graph *g, int32_t *d_truss, int64_t cap,
  * over all rounds (= m), [3] largest round, [4] compactions of the edge list,
  * [5 + i] rounds whose removal count r has floor(log2 r) = i, [37]
  * candidate third vertices examined, [38] of them searched (edge alive),
- * [39] triangles found, [40] triangles destroyed (each exactly once). */
+ * [39] triangles found still present, [40] triangles destroyed (each
+ * exactly once).  Edges whose support is 0 when they are peeled have no
+ * triangle left and are not scanned; a scan stops once it has found as many
+ * present triangles as the edge's support. */
 gc_status gc_graph_truss_stats(const gc_graph *g, int64_t *h_stats, int32_t cap);
 
 /* ------------------------------------------------------------------------ */

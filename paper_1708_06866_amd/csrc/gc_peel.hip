@@ -46,19 +46,20 @@ __device__ __forceinline__ int32_t find_col(const int32_t *__restrict__ col, int
   return (lo < end && col[lo] == key) ? lo : -1;
 }
 
-// Triangle {p, q1, q2} seen from frontier edge p (q2 < 0: no triangle).  Every
-// active lane of the wave calls this together, so the next-frontier appends
-// are aggregated per wave.
-__device__ __forceinline__ bool destroy(bool found, int32_t p, int32_t q1, int32_t q2,
-                                        int32_t thr, const uint8_t *__restrict__ state,
-                                        int32_t *__restrict__ sup, int32_t *__restrict__ next,
-                                        int32_t *__restrict__ next_count) {
-  bool t1 = false, t2 = false, ours = false;
+// Triangle {p, q1, q2} seen from frontier edge p (found == false: no
+// triangle).  Every active lane of the wave calls this together, so the
+// next-frontier appends are aggregated per wave.  Returns bit 0: the triangle
+// is still present (no edge of it died in an earlier round); bit 1: this call
+// destroyed it (p is its smallest frontier edge).
+__device__ __forceinline__ int destroy(bool found, int32_t p, int32_t q1, int32_t q2,
+                                       int32_t thr, const uint8_t *__restrict__ state,
+                                       int32_t *__restrict__ sup, int32_t *__restrict__ next,
+                                       int32_t *__restrict__ next_count) {
+  bool t1 = false, t2 = false, present = false, ours = false;
   if (found) {
     const uint8_t s1 = state[q1], s2 = state[q2];
-    // skip if destroyed in an earlier round, or owned by a smaller frontier edge
-    ours = s1 != EDGE_DEAD && s2 != EDGE_DEAD &&
-           !(s1 == EDGE_FRONT && q1 < p) && !(s2 == EDGE_FRONT && q2 < p);
+    present = s1 != EDGE_DEAD && s2 != EDGE_DEAD;
+    ours = present && !(s1 == EDGE_FRONT && q1 < p) && !(s2 == EDGE_FRONT && q2 < p);
     if (ours) {
       if (s1 == EDGE_ALIVE) t1 = atomicSub(&sup[q1], 1) == thr;
       if (s2 == EDGE_ALIVE) t2 = atomicSub(&sup[q2], 1) == thr;
@@ -68,7 +69,7 @@ __device__ __forceinline__ bool destroy(bool found, int32_t p, int32_t q1, int32
   if (t1) next[at] = q1;
   at = wave_append(t2, next_count);
   if (t2) next[at] = q2;
-  return ours;
+  return (present ? 1 : 0) | (ours ? 2 : 0);
 }
 
 constexpr int PEEL_U = 4;  // candidates per lane in flight
@@ -164,9 +165,12 @@ __device__ __forceinline__ PeelCase peel_case(const PeelEdge &e, int32_t p, int 
 //   a < x < b  head of a's row before p (a -> x)  vs  b's in-list, sources in (a, b)
 //   x < a      a's in-list (x -> a)               vs  b's in-list, sources < a
 // Each lane takes PEEL_U candidates of A per step (stride 64 * wpe), searched
-// in lockstep.
+// in lockstep.  When a round starts, the support of a frontier edge equals the
+// number of its triangles still present (every earlier destruction of one of
+// them decremented it while the edge was alive), so an edge with support 0 is
+// skipped and a wave that scans an edge alone stops after that many.
 // `work` (optional) holds 4 counters per wave: candidates, searches,
-// triangles found, triangles destroyed.
+// triangles found still present, triangles destroyed.
 __global__ __launch_bounds__(PBLK) void k_peel(CsrView c, const int32_t *__restrict__ front,
                                                int32_t nfront, int32_t thr, int32_t wpe,
                                                int32_t *__restrict__ sup,
@@ -183,16 +187,22 @@ __global__ __launch_bounds__(PBLK) void k_peel(CsrView c, const int32_t *__restr
   const int32_t stride = 64 * wpe;
   for (int64_t f = gw / wpe; f < nfront && gw < groups * wpe; f += groups) {
     const int32_t p = front[f];
+    // p's support is the number of its triangles still present: none -> no
+    // work; and a wave that scans p alone may stop once it has seen them all
+    const int32_t need = sup[p];
+    if (need == 0) continue;
+    int32_t seen = 0;
     const int32_t a = c.src[p], b = c.col[p];
     const PeelEdge e = peel_edge(c, a, b);
 #pragma unroll 1
-    for (int cs = 0; cs < 3; ++cs) {
+    for (int cs = 0; cs < 3 && !(wpe == 1 && seen >= need); ++cs) {
       const PeelCase pc = peel_case(e, p, cs);
       const int32_t nA = pc.nA, A0 = pc.A0, B0 = pc.B0, B1 = pc.B0 + pc.nB;
       if (nA == 0) continue;
       const bool A_in = pc.flags & 1u, B_in = pc.flags & 2u, a_is_ax = pc.flags & 4u;
       const int32_t *keysB = B_in ? c.in_src : c.col;
-      for (int32_t t0 = sub * 64 + lane; t0 - lane < nA; t0 += stride * PEEL_U) {
+      for (int32_t t0 = sub * 64 + lane; t0 - lane < nA && !(wpe == 1 && seen >= need);
+           t0 += stride * PEEL_U) {
         int32_t qk[PEEL_U], key[PEEL_U], lo[PEEL_U], hi[PEEL_U], idx[PEEL_U];
 #pragma unroll
         for (int u = 0; u < PEEL_U; ++u) {
@@ -224,9 +234,10 @@ __global__ __launch_bounds__(PBLK) void k_peel(CsrView c, const int32_t *__restr
             q1 = a_is_ax ? qk[u] : other;  // edge between a and x
             q2 = a_is_ax ? other : qk[u];  // edge between b and x
           }
-          const bool fnd = q1 >= 0;
-          n_found += fnd;
-          n_ours += destroy(fnd, p, q1, q2, thr, state, sup, next, next_count);
+          const int r = destroy(q1 >= 0, p, q1, q2, thr, state, sup, next, next_count);
+          n_found += r & 1;
+          n_ours += r >> 1;
+          seen += __popcll(__ballot(r & 1));
         }
       }
     }
@@ -258,17 +269,21 @@ constexpr int FLAT_TILE = PBLK * PEEL_U;  // candidates per block step
 constexpr int FLAT_BLOCKS = 2048;         // 8 blocks (32 waves) per CU
 
 __global__ __launch_bounds__(PBLK) void k_peel_plan(CsrView c, const int32_t *__restrict__ front,
-                                                    int32_t nfront, int4 *__restrict__ plan,
+                                                    int32_t nfront,
+                                                    const int32_t *__restrict__ sup,
+                                                    int4 *__restrict__ plan,
                                                     int32_t *__restrict__ cnt) {
   for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < nfront;
        f += (int64_t)gridDim.x * blockDim.x) {
     const int32_t p = front[f];
+    const bool none = sup[p] == 0;  // no triangle of p is left: no candidates
     const PeelEdge e = peel_edge(c, c.src[p], c.col[p]);
     int32_t tot = 0, cum[2] = {0, 0};
     uint32_t flags = 0;
 #pragma unroll
     for (int cs = 0; cs < 3; ++cs) {
-      const PeelCase pc = peel_case(e, p, cs);
+      PeelCase pc = peel_case(e, p, cs);
+      if (none) pc.nA = 0;
       plan[4 * f + 1 + cs] = make_int4(pc.A0, pc.nA, pc.B0, pc.nB);
       flags |= pc.flags << (3 * cs);
       tot += pc.nA;
@@ -376,9 +391,9 @@ __global__ __launch_bounds__(PBLK) void k_peel_flat(CsrView c, const int4 *__res
           q1 = a_is_ax ? qk[u] : other;  // edge between a and x
           q2 = a_is_ax ? other : qk[u];  // edge between b and x
         }
-        const bool fnd = q1 >= 0;
-        n_found += fnd;
-        n_ours += destroy(fnd, pk[u], q1, q2, thr, state, sup, next, next_count);
+        const int res = destroy(q1 >= 0, pk[u], q1, q2, thr, state, sup, next, next_count);
+        n_found += res & 1;
+        n_ours += res >> 1;
       }
       __syncthreads();  // s_rel and s_f read by every lane
       if (tid == 0 && t0 + FLAT_TILE < hi) s_f = fc + upper_bound_t(s_rel, nv, (int64_t)FLAT_TILE) - 1;
@@ -628,8 +643,10 @@ gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStre
   int32_t kmax = 2;
   const int64_t peel_waves = 256 * 32;  // 32 waves per CU
   static_assert(FLAT_BLOCKS * (PBLK / 64) <= 256 * 32, "work counters sized for peel_waves");
-  // frontiers of at least this many edges take the load-balanced kernel
-  int64_t flat_min = 65536;
+  // frontiers of at least this many edges take the load-balanced kernel (by
+  // default none: with its early exit the wave-per-edge kernel was faster on
+  // the R-MAT workloads; GC_PEEL_FLAT_MIN selects the split)
+  int64_t flat_min = (int64_t)1 << 40;
   if (const char *env = std::getenv("GC_PEEL_FLAT_MIN")) flat_min = std::atoll(env);
   int64_t *stats = g->peel_stats;
   for (int i = 0; i < 41; ++i) stats[i] = 0;
@@ -693,7 +710,7 @@ gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStre
         GC_TRY(dalloc(ps.offs, sizeof(int64_t) * ((size_t)nfront + 1)));
         int4 *plan = static_cast<int4 *>(ps.plan.ptr);
         int64_t *offs = static_cast<int64_t *>(ps.offs.ptr);
-        k_peel_plan<<<gsz(nfront), PBLK, 0, s>>>(c, front, nfront, plan, flag);
+        k_peel_plan<<<gsz(nfront), PBLK, 0, s>>>(c, front, nfront, sup, plan, flag);
         GC_LAUNCH_CHECK();
         GC_TRY(g->ws.reserve(scan_scratch_bytes((int64_t)nfront + 1)));
         GC_TRY(exclusive_scan64(flag, offs, nfront,

@@ -261,7 +261,20 @@ DIGEST_GENS = {
     "rmat_s18_ef16_seed1": lambda: gg.rmat(18, 16, seed=1),
     "rmat_s20_ef16_seed1": lambda: gg.rmat(20, 16, seed=1),
     "er_n20_m16n_seed2": lambda: gg.er(1 << 20, 16 << 20, seed=2),
+    # the full-size workloads (decomposition digests only up to scale 20;
+    # the scale-24 decomposition is checked by properties below)
+    "rmat_s24_ef16_seed1": lambda: _rmat24(),
+    "er_n24_m16n_seed2": lambda: gg.er(1 << 24, 16 << 24, seed=2),
 }
+
+
+_RMAT24 = []
+
+
+def _rmat24():
+    if not _RMAT24:
+        _RMAT24.append(gg.rmat(24, 16, seed=1))
+    return _RMAT24[0]
 
 
 @pytest.mark.parametrize("name", sorted(DIGEST_GENS))
@@ -286,6 +299,43 @@ def test_against_oracle_digest(name):
             assert mk == rec["m_k"]
             assert sha(mask.cpu().numpy()) == rec["mask_sha256"]
     g.free()
+
+
+def test_scale24_decomposition_properties():
+    """Full decomposition of the scale-24 R-MAT graph (too large for the
+    oracle's decomposition): every triangle is destroyed exactly once and every
+    edge removed once; no truss number exceeds support + 2; and the top level
+    (edges with truss number kmax) is a kmax-truss whose minimum support, counted
+    here by the masked product (A A) .* A on that subgraph, is exactly kmax - 2
+    (larger would make it a (kmax+1)-truss)."""
+    gold = _golden().get("rmat_s24_ef16_seed1")
+    if gold is None:
+        pytest.skip("no stored oracle digest for the scale-24 graph")
+    src, dst, n = _rmat24()
+    say("case scale-24 decomposition")
+    g = gc.build_graph(src, dst, n)
+    tau, kmax = g.truss_decomposition()
+    st = g.truss_stats()
+    say("stats", {k: v for k, v in st.items() if k != "rounds_by_log2_size"})
+    assert st["triangles_destroyed"] == gold["triangles"]
+    assert st["removed"] == gold["m"]
+    sup = g.edge_support()
+    assert bool((tau >= 2).all()) and bool((tau <= sup + 2).all())
+    assert int(tau.max()) == kmax
+    top = (tau == kmax).nonzero().flatten()
+    u, v = g.edges()
+    tu, tv = u[top].cpu().numpy(), v[top].cpu().numpy()
+    say("top level", kmax, len(tu))
+    g.free()
+    import scipy.sparse as sp
+    ids, inv = np.unique(np.concatenate([tu, tv]), return_inverse=True)
+    a, b = inv[:len(tu)], inv[len(tu):]
+    k = len(ids)
+    A = sp.coo_matrix((np.ones(2 * len(a), np.int64), (np.r_[a, b], np.r_[b, a])),
+                      shape=(k, k)).tocsr()
+    S = (A @ A).multiply(A).tocsr()
+    tsup = np.asarray(S[a, b]).ravel()
+    assert int(tsup.min()) == kmax - 2
 
 
 def test_decomposition_peel_equals_rounds(monkeypatch):
