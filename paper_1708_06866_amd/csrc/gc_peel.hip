@@ -26,8 +26,6 @@
 //
 // Results equal the rounds of Alg. 4 (bulk removal per round, same frontier
 // sets); only the work per round differs.
-#include <cstdlib>
-
 #include "gc_graph.h"
 
 namespace gc {
@@ -158,7 +156,9 @@ __device__ __forceinline__ PeelCase peel_case(const PeelEdge &e, int32_t p, int 
   return pc;
 }
 
-// One round of level k.  `wpe` waves share each frontier edge p = (a -> b).
+// One round of level k over the frontier front[0, *front_count); the size is
+// read here, so rounds can be queued without the host knowing it.  `wpe`
+// waves share each frontier edge p = (a -> b).
 // Its triangles {a, b, x} split by the rank of x, and each case intersects two
 // sorted lists, iterating the shorter (A) and searching the longer (B):
 //   x > b      tail of a's row after p (a -> x)   vs  b's row (b -> x)
@@ -172,8 +172,8 @@ __device__ __forceinline__ PeelCase peel_case(const PeelEdge &e, int32_t p, int 
 // `work` (optional) holds 4 counters per wave: candidates, searches,
 // triangles found still present, triangles destroyed.
 __global__ __launch_bounds__(PBLK) void k_peel(CsrView c, const int32_t *__restrict__ front,
-                                               int32_t nfront, int32_t thr, int32_t wpe,
-                                               int32_t *__restrict__ sup,
+                                               const int32_t *__restrict__ front_count,
+                                               int32_t thr, int32_t *__restrict__ sup,
                                                const uint8_t *__restrict__ state,
                                                int32_t *__restrict__ next,
                                                int32_t *__restrict__ next_count,
@@ -182,6 +182,10 @@ __global__ __launch_bounds__(PBLK) void k_peel(CsrView c, const int32_t *__restr
   int32_t n_cand = 0, n_search = 0, n_found = 0, n_ours = 0;  // per-lane work counters
   const int64_t gw = ((int64_t)blockIdx.x * PBLK + threadIdx.x) >> 6;
   const int64_t nw = ((int64_t)gridDim.x * PBLK) >> 6;
+  const int32_t nfront = *front_count;
+  // keep every wave busy: a small frontier shares each edge among wpe waves
+  int32_t wpe = 1;
+  while (wpe < 16 && (int64_t)nfront * wpe * 2 <= nw) wpe *= 2;
   const int64_t groups = nw / wpe;
   const int32_t sub = (int32_t)(gw % wpe);
   const int32_t stride = 64 * wpe;
@@ -254,165 +258,6 @@ __global__ __launch_bounds__(PBLK) void k_peel(CsrView c, const int32_t *__restr
   }
 }
 
-// ---- load-balanced round: every lane takes one candidate ----
-//
-// For frontiers of many edges, most edges have short lists and a wave per edge
-// leaves most lanes idle.  The plan kernel writes each edge's three cases and
-// its candidate count (at least 1, so that every edge owns a candidate index);
-// an exclusive scan of the counts numbers all candidates of the round; the
-// flat kernel splits that range evenly over its blocks, and each lane finds
-// the edge of its candidate by binary search in the block's slice of the scan.
-// Per edge the plan holds 4 int4: {p, c1, c2, flags}, where case 1 starts at
-// candidate c1 and case 2 at c2, then {A0, nA, B0, nB} of cases 0, 1, 2.
-
-constexpr int FLAT_TILE = PBLK * PEEL_U;  // candidates per block step
-constexpr int FLAT_BLOCKS = 2048;         // 8 blocks (32 waves) per CU
-
-__global__ __launch_bounds__(PBLK) void k_peel_plan(CsrView c, const int32_t *__restrict__ front,
-                                                    int32_t nfront,
-                                                    const int32_t *__restrict__ sup,
-                                                    int4 *__restrict__ plan,
-                                                    int32_t *__restrict__ cnt) {
-  for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < nfront;
-       f += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t p = front[f];
-    const bool none = sup[p] == 0;  // no triangle of p is left: no candidates
-    const PeelEdge e = peel_edge(c, c.src[p], c.col[p]);
-    int32_t tot = 0, cum[2] = {0, 0};
-    uint32_t flags = 0;
-#pragma unroll
-    for (int cs = 0; cs < 3; ++cs) {
-      PeelCase pc = peel_case(e, p, cs);
-      if (none) pc.nA = 0;
-      plan[4 * f + 1 + cs] = make_int4(pc.A0, pc.nA, pc.B0, pc.nB);
-      flags |= pc.flags << (3 * cs);
-      tot += pc.nA;
-      if (cs < 2) cum[cs] = tot;
-    }
-    plan[4 * f] = make_int4(p, cum[0], cum[1], (int32_t)flags);
-    cnt[f] = tot > 0 ? tot : 1;
-  }
-}
-
-// First index i of a[0, n) with a[i] > x (a sorted).
-template <class T>
-__device__ __forceinline__ int32_t upper_bound_t(const T *a, int32_t n, int64_t x) {
-  int32_t lo = 0, hi = n;
-  while (lo < hi) {
-    const int32_t mid = lo + ((hi - lo) >> 1);
-    if ((int64_t)a[mid] <= x) lo = mid + 1; else hi = mid;
-  }
-  return lo;
-}
-
-// offs[0, nfront] is the exclusive scan of the plan's counts; offs[nfront] is
-// the round's candidate total, read here so the host need not know it.
-__global__ __launch_bounds__(PBLK) void k_peel_flat(CsrView c, const int4 *__restrict__ plan,
-                                                    const int64_t *__restrict__ offs,
-                                                    int32_t nfront, int32_t thr,
-                                                    int32_t *__restrict__ sup,
-                                                    const uint8_t *__restrict__ state,
-                                                    int32_t *__restrict__ next,
-                                                    int32_t *__restrict__ next_count,
-                                                    unsigned long long *__restrict__ work) {
-  // The block's slice of offs, relative to the step's first candidate t0 and
-  // clamped to int32: a candidate's position in its edge and every index
-  // derived from it then stay 32-bit values well inside range, although the
-  // round's total (and so t0) may exceed 2^31.
-  __shared__ int32_t s_rel[FLAT_TILE + 1];
-  __shared__ int32_t s_f;
-  const int tid = threadIdx.x, lane = tid & 63;
-  int32_t n_cand = 0, n_search = 0, n_found = 0, n_ours = 0;
-  const int64_t total = offs[nfront];
-  int64_t chunk = (total + gridDim.x - 1) / gridDim.x;
-  chunk = (chunk + FLAT_TILE - 1) / FLAT_TILE * FLAT_TILE;
-  const int64_t lo = (int64_t)blockIdx.x * chunk;
-  const int64_t hi = lo + chunk < total ? lo + chunk : total;
-  if (lo < hi) {  // the same for the whole block
-    if (tid == 0) s_f = upper_bound_t(offs, nfront + 1, lo) - 1;
-    __syncthreads();
-    for (int64_t t0 = lo; t0 < hi; t0 += FLAT_TILE) {
-      // edges [fc, fc + nv - 1) hold every candidate of this step: each edge
-      // has at least one, and edge fc holds t0 (so s_rel[0] is in (-2^31, 0])
-      const int32_t fc = s_f;
-      const int32_t nv = nfront + 1 - fc < FLAT_TILE + 1 ? nfront + 1 - fc : FLAT_TILE + 1;
-      const int32_t lim = hi - t0 < FLAT_TILE ? (int32_t)(hi - t0) : FLAT_TILE;
-      for (int i = tid; i < nv; i += PBLK) {
-        const int64_t d = offs[fc + i] - t0;
-        s_rel[i] = d < (int64_t)INT32_MAX ? (int32_t)d : INT32_MAX;
-      }
-      __syncthreads();
-      int32_t pk[PEEL_U], qk[PEEL_U], key[PEEL_U], blo[PEEL_U], bhi[PEEL_U], idx[PEEL_U];
-      uint32_t fl[PEEL_U];
-      const int32_t *arr[PEEL_U];
-#pragma unroll
-      for (int u = 0; u < PEEL_U; ++u) {
-        const int32_t loc = u * PBLK + tid;  // candidate t0 + loc
-        pk[u] = -1;
-        qk[u] = -1;
-        key[u] = 0;
-        blo[u] = 0;
-        bhi[u] = 0;
-        fl[u] = 0;
-        arr[u] = c.col;
-        if (loc < lim) {
-          const int32_t j = upper_bound_t(s_rel, nv, loc) - 1;
-          const int64_t f = (int64_t)fc + j;
-          int32_t r = loc - s_rel[j];  // position within edge f's candidates
-          const int4 h = plan[4 * f];
-          const int cs = r < h.y ? 0 : (r < h.z ? 1 : 2);
-          r -= cs == 0 ? 0 : (cs == 1 ? h.y : h.z);
-          const int4 pc = plan[4 * f + 1 + cs];
-          if (r < pc.y) {  // not the placeholder of an edge without candidates
-            ++n_cand;
-            const uint32_t flags = ((uint32_t)h.w >> (3 * cs)) & 7u;
-            const int32_t i = pc.x + r;
-            const int32_t q = (flags & 1u) ? c.in_slot[i] : i;
-            if (state[q] != EDGE_DEAD) {
-              ++n_search;
-              pk[u] = h.x;
-              qk[u] = q;
-              fl[u] = flags;
-              key[u] = (flags & 1u) ? c.in_src[i] : c.col[i];
-              blo[u] = pc.z;
-              bhi[u] = pc.z + pc.w;
-              arr[u] = (flags & 2u) ? c.in_src : c.col;
-            }
-          }
-        }
-      }
-      find_many(arr, blo, bhi, key, idx);
-#pragma unroll
-      for (int u = 0; u < PEEL_U; ++u) {
-        int32_t q1 = -1, q2 = -1;
-        if (qk[u] >= 0 && idx[u] >= 0) {
-          const int32_t other = (fl[u] & 2u) ? c.in_slot[idx[u]] : idx[u];
-          const bool a_is_ax = fl[u] & 4u;
-          q1 = a_is_ax ? qk[u] : other;  // edge between a and x
-          q2 = a_is_ax ? other : qk[u];  // edge between b and x
-        }
-        const int res = destroy(q1 >= 0, pk[u], q1, q2, thr, state, sup, next, next_count);
-        n_found += res & 1;
-        n_ours += res >> 1;
-      }
-      __syncthreads();  // s_rel and s_f read by every lane
-      if (tid == 0 && t0 + FLAT_TILE < hi) s_f = fc + upper_bound_t(s_rel, nv, (int64_t)FLAT_TILE) - 1;
-      __syncthreads();
-    }
-  }
-  if (work) {
-    const int64_t gw = ((int64_t)blockIdx.x * PBLK + tid) >> 6;
-    const int32_t a0 = wave_sum_i32(n_cand), a1 = wave_sum_i32(n_search);
-    const int32_t a2 = wave_sum_i32(n_found), a3 = wave_sum_i32(n_ours);
-    if (lane == 0) {  // this wave's own slots
-      work[gw * 4 + 0] += (unsigned long long)a0;
-      work[gw * 4 + 1] += (unsigned long long)a1;
-      work[gw * 4 + 2] += (unsigned long long)a2;
-      work[gw * 4 + 3] += (unsigned long long)a3;
-    }
-  }
-}
-
 __global__ void k_sum_work(const unsigned long long *__restrict__ w, int64_t nw,
                            unsigned long long *__restrict__ out) {
   unsigned long long acc[4] = {0, 0, 0, 0};
@@ -425,12 +270,16 @@ __global__ void k_sum_work(const unsigned long long *__restrict__ w, int64_t nw,
   }
 }
 
-// Retire the frontier (truss number k - 1) and mark the next one.
-__global__ void k_advance(const int32_t *__restrict__ front, int32_t nfront,
+// Retire the frontier (truss number k - 1) and mark the next one.  Also
+// clears the counter the round after next appends to (the one this round's
+// predecessor read), and keeps the round statistics: st[0] rounds, st[1]
+// edges removed, st[2] largest round, st[3 + i] rounds with floor(log2 r) = i.
+__global__ void k_advance(const int32_t *__restrict__ front, const int32_t *__restrict__ front_count,
                           const int32_t *__restrict__ next, const int32_t *__restrict__ next_count,
-                          uint8_t *__restrict__ state, const int32_t *__restrict__ eid,
-                          int32_t *__restrict__ tau, int32_t tau_val) {
-  const int32_t nn = *next_count;
+                          int32_t *__restrict__ spare_count, uint8_t *__restrict__ state,
+                          const int32_t *__restrict__ eid, int32_t *__restrict__ tau,
+                          int32_t tau_val, long long *__restrict__ st) {
+  const int32_t nfront = *front_count, nn = *next_count;
   const int64_t lim = nfront > nn ? nfront : nn;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < lim;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -440,11 +289,31 @@ __global__ void k_advance(const int32_t *__restrict__ front, int32_t nfront,
       tau[eid[p]] = tau_val;
     }
   }
-  __threadfence();
-  // the next frontier is disjoint from the current one
+  // the next frontier is disjoint from the current one (its edges were alive
+  // during the round), so the two loops never store to the same state byte
+  // and need no ordering between them
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nn;
        i += (int64_t)gridDim.x * blockDim.x)
     state[next[i]] = EDGE_FRONT;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *spare_count = 0;
+    if (nfront > 0) {
+      st[0] += 1;
+      st[1] += nfront;
+      if (nfront > st[2]) st[2] = nfront;
+      st[3 + (31 - __clz(nfront))] += 1;
+    }
+  }
+}
+
+// Start of the rounds of a level: the frontier count (from the collecting
+// scan) becomes counter 0, counters 1 and 2 start at zero.
+__global__ void k_level_start(int32_t *__restrict__ cnt, const int32_t *__restrict__ nfront) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    cnt[0] = *nfront;
+    cnt[1] = 0;
+    cnt[2] = 0;
+  }
 }
 
 __global__ void k_alive_flags(const int32_t *__restrict__ list, int32_t L,
@@ -548,13 +417,13 @@ __global__ void k_rows2(const int32_t *__restrict__ row_ptr, const int32_t *__re
 static unsigned gsz(int64_t work) { return grid_for(work, 256, 65536); }
 
 struct PeelState {
-  DeviceBuffer sup[2], state[2], list[2], front[2], flag, pos, misc, work, plan, offs;
+  DeviceBuffer sup[2], state[2], list[2], front[2], flag, pos, misc, work, ctl;
   int cur = 0;  // which sup/state buffer is live
   ~PeelState() {
     for (int i = 0; i < 2; ++i) {
       dfree(sup[i]); dfree(state[i]); dfree(list[i]); dfree(front[i]);
     }
-    dfree(flag); dfree(pos); dfree(misc); dfree(work); dfree(plan); dfree(offs);
+    dfree(flag); dfree(pos); dfree(misc); dfree(work); dfree(ctl);
   }
 };
 
@@ -634,26 +503,34 @@ gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStre
   }
   int32_t *list = static_cast<int32_t *>(ps.list[0].ptr);
   int32_t *list2 = static_cast<int32_t *>(ps.list[1].ptr);
-  int32_t *front = static_cast<int32_t *>(ps.front[0].ptr);
-  int32_t *next = static_cast<int32_t *>(ps.front[1].ptr);
+  // frontier buffers: a level collects into buf[0]; round r reads buf[r & 1]
+  // and appends the next frontier to buf[(r + 1) & 1]
+  int32_t *buf[2] = {static_cast<int32_t *>(ps.front[0].ptr),
+                     static_cast<int32_t *>(ps.front[1].ptr)};
   k_iota<<<gsz(m), 256, 0, s>>>(list, m);
   GC_LAUNCH_CHECK();
   int32_t L = m;
   int next_store = 0;
   int32_t kmax = 2;
   const int64_t peel_waves = 256 * 32;  // 32 waves per CU
-  static_assert(FLAT_BLOCKS * (PBLK / 64) <= 256 * 32, "work counters sized for peel_waves");
-  // frontiers of at least this many edges take the load-balanced kernel (by
-  // default none: with its early exit the wave-per-edge kernel was faster on
-  // the R-MAT workloads; GC_PEEL_FLAT_MIN selects the split)
-  int64_t flat_min = (int64_t)1 << 40;
-  if (const char *env = std::getenv("GC_PEEL_FLAT_MIN")) flat_min = std::atoll(env);
+  const unsigned peel_blocks = (unsigned)(peel_waves / (PBLK / 64));
   int64_t *stats = g->peel_stats;
   for (int i = 0; i < 41; ++i) stats[i] = 0;
   // per-wave work counters (candidates, searches, triangles), summed at the end
   GC_TRY(dalloc(ps.work, sizeof(unsigned long long) * 4 * (size_t)peel_waves + 64));
   unsigned long long *work = static_cast<unsigned long long *>(ps.work.ptr);
   GC_HIP(hipMemsetAsync(work, 0, sizeof(unsigned long long) * (4 * (size_t)peel_waves + 8), s));
+  // round control in device memory: three frontier counters (round r reads
+  // cnt[r % 3], appends to cnt[(r + 1) % 3]) and the round statistics
+  struct Ctl {
+    int32_t cnt[16];
+    long long st[40];
+  };
+  GC_TRY(dalloc(ps.ctl, sizeof(Ctl)));
+  Ctl *ctl = static_cast<Ctl *>(ps.ctl.ptr);
+  GC_HIP(hipMemsetAsync(ctl, 0, sizeof(Ctl), s));
+  Ctl h_ctl;
+  long long removed_base = 0;  // edges removed when L was last counted
 
   for (;;) {
     int32_t *sup = static_cast<int32_t *>(ps.sup[ps.cur].ptr);
@@ -678,7 +555,7 @@ gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStre
     const int32_t thr = k - 2;
     // compact the CSR when at least half of it is dead
     if ((int64_t)L * 2 < (int64_t)c.m) {
-      GC_TRY(compact_peel(g, ps, c, next_store, front, 0, s));
+      GC_TRY(compact_peel(g, ps, c, next_store, buf[0], 0, s));
       sup = static_cast<int32_t *>(ps.sup[ps.cur].ptr);
       state = static_cast<uint8_t *>(ps.state[ps.cur].ptr);
       k_iota<<<gsz(c.m), 256, 0, s>>>(list, c.m);
@@ -689,65 +566,52 @@ gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStre
     GC_LAUNCH_CHECK();
     GC_TRY(g->ws.reserve(scan_scratch_bytes((int64_t)L + 1)));
     GC_TRY(exclusive_scan(flag, pos, L, g->ws.take<char>(scan_scratch_bytes((int64_t)L + 1)), s));
-    k_collect_scatter<<<gsz(L), 256, 0, s>>>(list, L, flag, pos, state, front);
+    k_collect_scatter<<<gsz(L), 256, 0, s>>>(list, L, flag, pos, state, buf[0]);
+    GC_LAUNCH_CHECK();
+    k_level_start<<<1, 64, 0, s>>>(ctl->cnt, pos + L);
     GC_LAUNCH_CHECK();
     int32_t nfront = 0;
     GC_HIP(hipMemcpyAsync(&nfront, pos + L, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     GC_HIP(hipStreamSynchronize(s));
-    int64_t dead_since = 0;
-    if (nfront > 0) ++stats[0];
-    // ---- rounds of level k ----
-    while (nfront > 0) {
-      kmax = k - 1 > kmax ? k - 1 : kmax;
-      ++stats[1];
-      stats[2] += nfront;
-      if (nfront > stats[3]) stats[3] = nfront;
-      ++stats[5 + (31 - __builtin_clz((unsigned)nfront))];
-      k_set_i32<<<1, 64, 0, s>>>(misc, 0, 0);
-      if (nfront >= flat_min) {
-        // load-balanced over candidates
-        GC_TRY(dalloc(ps.plan, sizeof(int4) * 4 * (size_t)nfront));
-        GC_TRY(dalloc(ps.offs, sizeof(int64_t) * ((size_t)nfront + 1)));
-        int4 *plan = static_cast<int4 *>(ps.plan.ptr);
-        int64_t *offs = static_cast<int64_t *>(ps.offs.ptr);
-        k_peel_plan<<<gsz(nfront), PBLK, 0, s>>>(c, front, nfront, sup, plan, flag);
+    if (nfront == 0) continue;
+    ++stats[0];
+    kmax = k - 1 > kmax ? k - 1 : kmax;
+    // ---- rounds of level k, queued in batches without waiting for their
+    // sizes (a round whose frontier is empty does nothing); the host looks at
+    // the counters between batches, to stop and to compact ----
+    int r = 0, batch = 1;
+    for (;;) {
+      for (int i = 0; i < batch; ++i, ++r) {
+        int32_t *fr = buf[r & 1], *nx = buf[(r + 1) & 1];
+        int32_t *cf = &ctl->cnt[r % 3], *cn = &ctl->cnt[(r + 1) % 3], *cz = &ctl->cnt[(r + 2) % 3];
+        k_peel<<<peel_blocks, PBLK, 0, s>>>(c, fr, cf, thr, sup, state, nx, cn, work);
         GC_LAUNCH_CHECK();
-        GC_TRY(g->ws.reserve(scan_scratch_bytes((int64_t)nfront + 1)));
-        GC_TRY(exclusive_scan64(flag, offs, nfront,
-                                g->ws.take<char>(scan_scratch_bytes((int64_t)nfront + 1)), s));
-        k_peel_flat<<<FLAT_BLOCKS, PBLK, 0, s>>>(c, plan, offs, nfront, thr, sup, state, next,
-                                                 misc, work);
-        GC_LAUNCH_CHECK();
-      } else {
-        // keep about peel_waves waves busy: share small frontiers' edges
-        // among several waves each
-        int32_t wpe = 1;
-        while (wpe < 16 && (int64_t)nfront * wpe * 2 <= peel_waves) wpe *= 2;
-        int64_t waves = (int64_t)nfront * wpe;
-        if (waves > peel_waves) waves = peel_waves;
-        const unsigned pg = (unsigned)((waves + (PBLK / 64) - 1) / (PBLK / 64));
-        k_peel<<<pg, PBLK, 0, s>>>(c, front, nfront, thr, wpe, sup, state, next, misc, work);
+        k_advance<<<4096, 256, 0, s>>>(fr, cf, nx, cn, cz, state, c.eid, tau, k - 1, ctl->st);
         GC_LAUNCH_CHECK();
       }
-      k_advance<<<gsz(nfront), 256, 0, s>>>(front, nfront, next, misc, state, c.eid, tau, k - 1);
-      GC_LAUNCH_CHECK();
-      int32_t nn = 0;
-      GC_HIP(hipMemcpyAsync(&nn, misc, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      GC_HIP(hipMemcpyAsync(&h_ctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
       GC_HIP(hipStreamSynchronize(s));
-      dead_since += nfront;
-      { int32_t *t = front; front = next; next = t; }
-      nfront = nn;
-      if (nfront > 0 && (L - dead_since) * 2 < (int64_t)c.m) {
-        GC_TRY(compact_peel(g, ps, c, next_store, front, nfront, s));
+      nfront = h_ctl.cnt[r % 3];
+      if (nfront == 0) break;
+      if ((L - (h_ctl.st[1] - removed_base)) * 2 < (int64_t)c.m) {
+        GC_TRY(compact_peel(g, ps, c, next_store, buf[r & 1], nfront, s));
         sup = static_cast<int32_t *>(ps.sup[ps.cur].ptr);
         state = static_cast<uint8_t *>(ps.state[ps.cur].ptr);
         k_iota<<<gsz(c.m), 256, 0, s>>>(list, c.m);
         GC_LAUNCH_CHECK();
         L = c.m;
-        dead_since = 0;
+        removed_base = h_ctl.st[1];
       }
+      batch = batch < 16 ? batch * 2 : 16;
     }
+    removed_base = h_ctl.st[1];
   }
+  GC_HIP(hipMemcpyAsync(&h_ctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+  GC_HIP(hipStreamSynchronize(s));
+  stats[1] = h_ctl.st[0];
+  stats[2] = h_ctl.st[1];
+  stats[3] = h_ctl.st[2];
+  for (int i = 0; i < 32; ++i) stats[5 + i] = h_ctl.st[3 + i];
   unsigned long long *wsum = work + 4 * (size_t)peel_waves;
   k_sum_work<<<1, 256, 0, s>>>(work, peel_waves, wsum);
   GC_LAUNCH_CHECK();
