@@ -300,7 +300,7 @@ def main():
     ap.add_argument("--scale", type=int, default=24)
     ap.add_argument("--ef", type=int, default=16)
     ap.add_argument("--seed", type=int, default=1)
-    ap.add_argument("--cpu-scale", type=int, default=17)
+    ap.add_argument("--cpu-scale", type=int, default=18)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-decomposition", action="store_true",
                     help="step = build + count only")
