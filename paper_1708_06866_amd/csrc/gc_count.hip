@@ -10,16 +10,17 @@
 // waves stream the tails of the chunk's in-edges, one tail per wave, 64
 // consecutive elements per step (coalesced), 4 steps in flight per lane.
 //
-// The LDS table is bucketed: 4 slots per 16-byte bucket, filled in slot
-// order, linear probing over buckets.  A probe reads one bucket
-// (ds_read_b128) and compares 4 keys; the key is absent as soon as a bucket
-// with a free slot is seen, so almost every probe ends after one read.  The
-// reads of the 4 in-flight elements are issued together.
+// Two LDS table layouts: linear probing over single slots (LinTable), and
+// buckets of 4 slots in 16 bytes, filled in slot order, with linear probing
+// over buckets (BucketTable): a probe reads one bucket (ds_read_b128) and
+// compares 4 keys, and the key is absent as soon as a bucket with a free slot
+// is seen.  The reads of the 4 in-flight elements are issued together.
 //
 // Degree bins pick the table size: d+(b) <= 32, 256, 2048 and 8192 (count) /
-// 4096 (support) with at most half the slots used (strategy 0) or a quarter
-// (strategy 1); longer out-lists are binary-searched in HBM (strategy 2, the
-// only one for the last bin).
+// 4096 (support).  Per bin the count chooses one of five strategies (see
+// count_strategy_valid): either layout with at most half or a quarter of the
+// slots used, or binary search of N+(b) in HBM (the only one for the last,
+// unbounded bin).  The autotuner times them per bin on the graph at hand.
 //
 // Support: a hit (a, b, c) adds one to each of its three edges.  a -> b (the
 // in-edge) is summed over the wave and added once per in-edge; b -> c (the
