@@ -49,6 +49,122 @@ def gen_inputs(workload: str, scale: int, ef: int, seed: int):
     raise ValueError(workload)
 
 
+class EnergyMeter:
+    """GPU energy over a region, read through amdsmi (read-only telemetry) on
+    the device matched to torch's by PCI bus: the accumulating energy counter
+    if it advances over the region, else socket power sampled every 5 ms and
+    integrated.  If neither is available stop() returns None and `source`
+    says why."""
+
+    def __init__(self, torch, dev):
+        import threading
+        self.h = None
+        self.source = "amdsmi"
+        self.samples = []
+        self.stop_ev = threading.Event()
+        self.th = threading.Thread(target=self._sample, daemon=True)
+        try:
+            import amdsmi
+            self.amdsmi = amdsmi
+            amdsmi.amdsmi_init()
+            handles = amdsmi.amdsmi_get_processor_handles()
+            props = torch.cuda.get_device_properties(dev)
+            bus = getattr(props, "pci_bus_id", None)
+            pick = None
+            for h in handles:
+                bdf = amdsmi.amdsmi_get_gpu_device_bdf(h)
+                if bus is not None and int(bdf.split(":")[1], 16) == int(bus):
+                    pick = h
+            if pick is None and len(handles) == 1:
+                pick = handles[0]
+            if pick is None:
+                raise RuntimeError("no amdsmi device matches PCI bus %s" % bus)
+            self.h = pick
+            self.bdf = amdsmi.amdsmi_get_gpu_device_bdf(pick)
+        except Exception as e:  # telemetry only: never fail the bench for it
+            self.source = "energy unavailable: %r" % (e,)
+
+    def _counter(self):
+        r = self.amdsmi.amdsmi_get_energy_count(self.h)
+        return r["energy_accumulator"] * r["counter_resolution"] * 1e-6  # uJ -> J
+
+    def _power(self):
+        info = self.amdsmi.amdsmi_get_power_info(self.h)
+        for key in ("current_socket_power", "socket_power", "average_socket_power"):
+            w = info.get(key)
+            if isinstance(w, (int, float)) and w > 0:
+                return float(w)
+        return None
+
+    def _sample(self):
+        while not self.stop_ev.is_set():
+            try:
+                w = self._power()
+            except Exception:
+                w = None
+            self.samples.append((time.perf_counter(), w))
+            time.sleep(0.005)
+
+    def start(self):
+        self.e0 = None
+        if self.h is None:
+            return
+        try:
+            self.e0 = self._counter()
+        except Exception:
+            self.e0 = None
+        self.th.start()
+
+    def stop(self):
+        if self.h is None:
+            return None
+        self.stop_ev.set()
+        self.th.join()
+        try:
+            if self.e0 is not None:
+                joules = self._counter() - self.e0
+                if joules > 0:
+                    self.source = "amdsmi energy counter, device %s" % self.bdf
+                    return joules
+        except Exception:
+            pass
+        pts = [(t, w) for t, w in self.samples if w is not None]
+        if len(pts) >= 2:
+            joules = sum(0.5 * (w0 + w1) * (t1 - t0)
+                         for (t0, w0), (t1, w1) in zip(pts, pts[1:]))
+            self.source = ("amdsmi socket power sampled every 5 ms (%d samples), device %s; "
+                           "the energy counter did not advance" % (len(pts), self.bdf))
+            return joules if joules > 0 else None
+        self.source = "energy unavailable: counter did not advance, no power samples"
+        return None
+
+
+class MemoryWatch:
+    """Peak device memory in use above the level at start(), polled."""
+
+    def __init__(self, torch, dev):
+        import threading
+        self.torch, self.dev = torch, dev
+        self.stop_ev = threading.Event()
+        self.min_free = None
+        self.th = threading.Thread(target=self._run, daemon=True)
+
+    def _run(self):
+        while not self.stop_ev.is_set():
+            free, _ = self.torch.cuda.mem_get_info(self.dev)
+            self.min_free = free if self.min_free is None else min(self.min_free, free)
+            time.sleep(0.002)
+
+    def start(self):
+        self.free0, _ = self.torch.cuda.mem_get_info(self.dev)
+        self.th.start()
+
+    def stop(self):
+        self.stop_ev.set()
+        self.th.join()
+        return int(self.free0 - self.min_free) if self.min_free is not None else None
+
+
 def algorithmic_bytes(row_ptr: np.ndarray, col: np.ndarray, chunk: int = 128) -> dict:
     """Bytes a count pass must move with no cache reuse.
 
@@ -300,6 +416,9 @@ def main():
     ap.add_argument("--scale", type=int, default=24)
     ap.add_argument("--ef", type=int, default=16)
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--input", default=None,
+                    help="edge file (TSV triples or Matrix Market) instead of a generated graph; "
+                         "read on the host before timing")
     ap.add_argument("--cpu-scale", type=int, default=18)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-decomposition", action="store_true",
@@ -341,8 +460,13 @@ def main():
         del x, y
 
     t = time.perf_counter()
-    src, dst, n = gen_inputs(args.workload, args.scale, args.ef, args.seed)
-    log("generated %d pairs in %.1fs" % (len(src), time.perf_counter() - t))
+    if args.input:
+        src, dst, n = gc.gc_read_edges(args.input)
+        log("read %d pairs from %s in %.1fs" % (len(src), args.input, time.perf_counter() - t))
+    else:
+        src, dst, n = gen_inputs(args.workload, args.scale, args.ef, args.seed)
+        log("generated %d pairs in %.1fs" % (len(src), time.perf_counter() - t))
+    read_s = time.perf_counter() - t
     d_src = torch.from_numpy(src).to(dev)
     d_dst = torch.from_numpy(dst).to(dev)
     del src, dst
@@ -403,13 +527,22 @@ def main():
 
     recs = []
     torch.cuda.synchronize()
+    energy = EnergyMeter(torch, dev)
+    memory = MemoryWatch(torch, dev)
+    graph_bytes = 0
+    energy.start()
+    memory.start()
     t0 = time.perf_counter()
     for i in range(args.steps):
         g = step(recs)
+        if i == 0:
+            graph_bytes = g.info()[2]
         g.free()
         log("step %d done" % i)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    joules = energy.stop()
+    peak_bytes = memory.stop()
 
     m = recs[-1][3]
     T = recs[-1][1]
@@ -440,14 +573,15 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "int32",
-        "data": "synthetic",
+        "data": "file" if args.input else "synthetic",
         "config": {
-            "workload": "%s scale %d edge factor %d seed %d%s; step = build CSR from raw pairs "
-                        "in HBM + triangle count + %s" % (
-                            "R-MAT (0.57,0.19,0.19,0.05)" if args.workload == "rmat" else "ER G(n,M)",
-                            args.scale, args.ef, args.seed,
-                            ", vertex ids permuted" if args.workload == "rmat" else "",
-                            "count only" if args.no_decomposition else "full truss decomposition"),
+            "workload": "%s; step = build CSR from raw pairs in HBM + triangle count + %s" % (
+                ("edge file %s" % os.path.basename(args.input)) if args.input else
+                "%s scale %d edge factor %d seed %d%s" % (
+                    "R-MAT (0.57,0.19,0.19,0.05)" if args.workload == "rmat" else "ER G(n,M)",
+                    args.scale, args.ef, args.seed,
+                    ", vertex ids permuted" if args.workload == "rmat" else ""),
+                "count only" if args.no_decomposition else "full truss decomposition"),
             "n_vertices": int(n), "m_edges": int(m), "adjacency_entries": int(2 * m),
             "triangles": int(T), "kmax": kmax,
         },
@@ -455,11 +589,23 @@ def main():
         "autotune": tuned,
         "decomposition_stats": record_stats or None,
         "tc_edges_per_s": m / (tc_ms / 1000.0),
+        # Sec. IV metrics beside the rate: energy of the timed steps from the
+        # GPU's energy counter, rate per watt, and device memory
+        "energy": ({"joules_per_step": joules / args.steps, "avg_watts": joules / wall,
+                    "edges_per_s_per_watt": value / (joules / wall),
+                    "source": energy.source} if joules
+                   else {"error": energy.source}),
+        "memory": {"graph_handle_bytes": int(graph_bytes),
+                   "step_peak_device_bytes": peak_bytes,
+                   "source": "hipMemGetInfo polled every 2 ms during the timed steps; "
+                             "graph handle from gc_graph_info"},
+        "input_read_s": read_s,
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": profiled_traffic(args.workload, args.scale, args.ef, args.seed,
-                                        tuned["strategy"] if tuned else None),
+            "traffic": None if args.input else profiled_traffic(
+                args.workload, args.scale, args.ef, args.seed,
+                tuned["strategy"] if tuned else None),
             "kernel": "triangle-count pass (k_tc_lds / k_tc_search, one dispatch per degree bin)",
             "traffic_source": "profiles/tc_count_rmat_s24.md (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
                               "calibrated; null unless taken on these kernels and strategies)",

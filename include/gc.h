@@ -292,6 +292,34 @@ gc_status gc_server_stats(gc_server *s, int64_t *h_stats);
 /* Stop the threads and release every resident graph (NULL is a no-op). */
 void gc_server_destroy(gc_server *s);
 
+/* ------------------------------------------------------------------------ */
+/* Edge files (host).                                                        */
+
+#define GC_FILE_AUTO 0 /* Matrix Market if the file starts with its banner, else TSV */
+#define GC_FILE_TSV 1  /* lines "u<TAB>v<TAB>w", ids 1..n, w ignored              */
+#define GC_FILE_MMIO 2 /* Matrix Market coordinate (pattern/integer/real), 1-based */
+
+/* Read an edge file in one of the two formats the paper's data come in
+ * (Sec. II: TSV triples u, v, 1 with ids 1..n, and MMIO).  Host code; reading
+ * is outside the timed path (Sec. IV-B).
+ * TSV: blank lines and lines starting with '#' or '%' are skipped; fields are
+ * separated by tabs or spaces; a third field (the weight) is ignored.
+ * MMIO: the banner must say "coordinate" (field pattern, integer or real);
+ * the size line gives n = max(rows, cols) and the entry count, which must
+ * match the entries present; symmetric files list each edge once (the
+ * normalisation of gc_build_csr symmetrises anyway).
+ * Call with h_src = h_dst = NULL to get *n_pairs (and *n_vertices for MMIO;
+ * -1 for TSV, whose n is only known after parsing); then with host arrays of
+ * cap >= *n_pairs entries, which receive the pairs with ids converted to
+ * 0-based (ready for gc_build_csr without GC_INPUT_ONE_BASED), and *n_vertices =
+ * the largest id (TSV) or max(rows, cols) (MMIO).  The caller owns the arrays.
+ * Errors: unreadable file, malformed line, bad banner or size line, or an
+ * entry count that differs from the size line -> GC_EINVAL; id 0, or above
+ * the MMIO size -> GC_ERANGE; an id above 2^31 - 1 -> GC_EOVERFLOW; cap too
+ * small -> GC_ECAPACITY.  The message names the offending line. */
+gc_status gc_read_edges(const char *path, int32_t format, int32_t *h_src, int32_t *h_dst,
+                        int64_t cap, int64_t *n_pairs, int64_t *n_vertices);
+
 /* Release a handle and its device memory (NULL is a no-op). */
 void gc_graph_free(gc_graph *g);
 

@@ -14,6 +14,7 @@ The functions carry the C names::
     gc_edge_support(g)                              # -> int32[m] (cuda)
     gc_ktruss(g, k)                                 # -> (uint8[m] mask, m_k)
     gc_truss_decomposition(g)                       # -> (int32[m] tau, kmax)
+    gc_read_edges(path)                             # TSV / Matrix Market file -> pairs
 
 ``Graph`` wraps a handle with the same operations as methods.
 """
@@ -35,6 +36,9 @@ GC_ENOMEM = -4
 GC_EDEVICE = -5
 GC_EOVERFLOW = -6
 GC_INPUT_ONE_BASED = 0x1
+GC_FILE_AUTO = 0
+GC_FILE_TSV = 1
+GC_FILE_MMIO = 2
 
 GC_PENDING = 1
 
@@ -108,6 +112,9 @@ def lib():
         L.gc_server_stats.argtypes = [P, P]
         L.gc_server_destroy.argtypes = [P]
         L.gc_server_destroy.restype = None
+        L.gc_read_edges.argtypes = [ctypes.c_char_p, i32, P, P, i64, ctypes.POINTER(i64),
+                                    ctypes.POINTER(i64)]
+        L.gc_read_edges.restype = i32
         for name in ("gc_server_create", "gc_server_set_mode", "gc_server_add_graph",
                      "gc_server_submit", "gc_server_poll", "gc_server_wait", "gc_server_stats"):
             getattr(L, name).restype = i32
@@ -322,9 +329,37 @@ def build_graph(src, dst, n_vertices: int, device="cuda", one_based: bool = Fals
 
 
 # ----------------------------------------------------------------------------
-# batches
+# edge files
 # ----------------------------------------------------------------------------
 import numpy as _np  # noqa: E402
+
+
+def gc_read_edges(path: str, fmt: int = GC_FILE_AUTO):
+    """Read a TSV or Matrix Market edge file (host): returns (src, dst, n),
+    int32 numpy arrays with 0-based ids and the vertex count."""
+    L = lib()
+    bpath = os.fsencode(path)
+    n_pairs = ctypes.c_int64(0)
+    n_vertices = ctypes.c_int64(0)
+    _check(L.gc_read_edges(bpath, fmt, None, None, 0, ctypes.byref(n_pairs),
+                           ctypes.byref(n_vertices)), "gc_read_edges")
+    src = _np.empty(n_pairs.value, dtype=_np.int32)
+    dst = _np.empty(n_pairs.value, dtype=_np.int32)
+    _check(L.gc_read_edges(bpath, fmt, src.ctypes.data_as(ctypes.c_void_p),
+                           dst.ctypes.data_as(ctypes.c_void_p), len(src),
+                           ctypes.byref(n_pairs), ctypes.byref(n_vertices)), "gc_read_edges")
+    return src, dst, int(n_vertices.value)
+
+
+def read_graph(path: str, fmt: int = GC_FILE_AUTO, device="cuda") -> Graph:
+    """Convenience: edge file -> Graph on ``device`` (reading is on the host)."""
+    src, dst, n = gc_read_edges(path, fmt)
+    return build_graph(src, dst, n, device=device)
+
+
+# ----------------------------------------------------------------------------
+# batches
+# ----------------------------------------------------------------------------
 
 
 class Batch:

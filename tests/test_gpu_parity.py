@@ -136,6 +136,36 @@ def test_er_and_rgg():
     check_all(*gg.rgg(1 << 13, 20.0, seed=3), "rgg13")
 
 
+def test_edge_files_to_gpu(tmp_path):
+    """The paper's input formats (Sec. II) end to end: the same R-MAT graph as
+    TSV triples (both directions, duplicates, 1-based) and as a symmetric
+    Matrix Market file (each edge once) gives, on the GPU, the oracle's
+    results on the generated pairs."""
+    src, dst, n = gg.rmat(12, 16, seed=11)
+    u, v = oracle.normalise(src, dst, n)
+    T = oracle.triangle_count(n, u, v)
+    sup = oracle.support(n, u, v, "listing")
+    tau_ref, kmax_ref = oracle.truss_decomposition(n, u, v, "peel")
+    tsv = str(tmp_path / "g.tsv")
+    np.savetxt(tsv, np.stack([src.astype(np.int64) + 1, dst.astype(np.int64) + 1,
+                              np.ones(len(src), np.int64)], 1), fmt="%d", delimiter="\t")
+    mtx = str(tmp_path / "g.mtx")
+    with open(mtx, "w") as f:
+        f.write("%%%%MatrixMarket matrix coordinate pattern symmetric\n%%\n%d %d %d\n" % (n, n, len(u)))
+        np.savetxt(f, np.stack([v.astype(np.int64) + 1, u.astype(np.int64) + 1], 1), fmt="%d")
+    for path in (tsv, mtx):
+        say("case edge file", os.path.basename(path))
+        s2, d2, n2 = gc.gc_read_edges(path)
+        g = gc.build_graph(s2, d2, n2)
+        gu, gv = g.edges()
+        assert np.array_equal(gu.cpu().numpy(), u) and np.array_equal(gv.cpu().numpy(), v)
+        assert g.triangle_count() == T
+        assert np.array_equal(g.edge_support().cpu().numpy(), sup)
+        tau, kmax = g.truss_decomposition()
+        assert kmax == kmax_ref and np.array_equal(tau.cpu().numpy(), tau_ref)
+        g.free()
+
+
 # ----------------------------------------------------------------------------
 # degree-bin boundaries, long in-lists, skew
 # ----------------------------------------------------------------------------
