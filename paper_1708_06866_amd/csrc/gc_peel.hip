@@ -347,10 +347,47 @@ __global__ void k_compact_list(const int32_t *__restrict__ list, int32_t L,
 }
 
 __global__ void k_collect_flags(const int32_t *__restrict__ list, int32_t L, int32_t thr,
+                                const uint8_t *__restrict__ state,
                                 const int32_t *__restrict__ sup, int32_t *__restrict__ flag) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < L;
-       i += (int64_t)gridDim.x * blockDim.x)
-    flag[i] = sup[list[i]] < thr ? 1 : 0;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t p = list[i];
+    flag[i] = state[p] == EDGE_ALIVE && sup[p] < thr ? 1 : 0;
+  }
+}
+
+// Minimum support and number of the live edges of `list` (which may also
+// hold dead ones): dmin = min, dalive += count.
+__global__ void k_level_min(const int32_t *__restrict__ list, int32_t L,
+                            const uint8_t *__restrict__ state, const int32_t *__restrict__ sup,
+                            int32_t *__restrict__ dmin, int32_t *__restrict__ dalive) {
+  int32_t v = 0x7fffffff, cnt = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < L;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t p = list[i];
+    if (state[p] == EDGE_ALIVE) {
+      v = min(v, sup[p]);
+      ++cnt;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    v = min(v, __shfl_xor(v, o, 64));
+    cnt += __shfl_xor(cnt, o, 64);
+  }
+  __shared__ int32_t wmin[4], wcnt[4];
+  if ((threadIdx.x & 63) == 0) {
+    wmin[threadIdx.x >> 6] = v;
+    wcnt[threadIdx.x >> 6] = cnt;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    v = min(min(wmin[0], wmin[1]), min(wmin[2], wmin[3]));
+    cnt = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+    if (cnt > 0) {
+      atomicMin(dmin, v);
+      atomicAdd(dalive, cnt);
+    }
+  }
 }
 
 __global__ void k_collect_scatter(const int32_t *__restrict__ list, int32_t L,
@@ -535,34 +572,40 @@ gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStre
   for (;;) {
     int32_t *sup = static_cast<int32_t *>(ps.sup[ps.cur].ptr);
     uint8_t *state = static_cast<uint8_t *>(ps.state[ps.cur].ptr);
-    // ---- level start: live edges, their minimum support ----
-    k_alive_flags<<<gsz(L), 256, 0, s>>>(list, L, state, flag);
-    GC_LAUNCH_CHECK();
-    GC_TRY(g->ws.reserve(scan_scratch_bytes((int64_t)L + 1)));
-    GC_TRY(exclusive_scan(flag, pos, L, g->ws.take<char>(scan_scratch_bytes((int64_t)L + 1)), s));
-    k_set_i32<<<1, 64, 0, s>>>(misc, 0, 0x7fffffff);
-    k_compact_list<<<grid_for(L, 256, 2048), 256, 0, s>>>(list, L, flag, pos, sup, list2,
-                                                          misc + 1);
+    // ---- level start: minimum support and number of the live edges ----
+    k_set_i32<<<1, 64, 0, s>>>(misc, 0x7fffffff, 0);
+    k_level_min<<<grid_for(L, 256, 2048), 256, 0, s>>>(list, L, state, sup, misc, misc + 1);
     GC_LAUNCH_CHECK();
     int32_t h[2];
-    GC_HIP(hipMemcpyAsync(&h[0], pos + L, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    GC_HIP(hipMemcpyAsync(&h[1], misc + 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    GC_HIP(hipMemcpyAsync(h, misc, sizeof(h), hipMemcpyDeviceToHost, s));
     GC_HIP(hipStreamSynchronize(s));
-    L = h[0];
-    if (L == 0) break;
-    { int32_t *t = list; list = list2; list2 = t; }
-    const int32_t k = h[1] + 3;   // first level that removes something
+    const int32_t alive = h[1];
+    if (alive == 0) break;
+    const int32_t k = h[0] + 3;   // first level that removes something
     const int32_t thr = k - 2;
-    // compact the CSR when at least half of it is dead
-    if ((int64_t)L * 2 < (int64_t)c.m) {
+    if ((int64_t)alive * 2 < (int64_t)c.m) {
+      // compact the CSR when at least half of it is dead
       GC_TRY(compact_peel(g, ps, c, next_store, buf[0], 0, s));
       sup = static_cast<int32_t *>(ps.sup[ps.cur].ptr);
       state = static_cast<uint8_t *>(ps.state[ps.cur].ptr);
       k_iota<<<gsz(c.m), 256, 0, s>>>(list, c.m);
       GC_LAUNCH_CHECK();
       L = c.m;
+    } else if ((int64_t)alive * 2 < (int64_t)L) {
+      // drop the dead entries of the live-edge list when they are the majority
+      k_alive_flags<<<gsz(L), 256, 0, s>>>(list, L, state, flag);
+      GC_LAUNCH_CHECK();
+      GC_TRY(g->ws.reserve(scan_scratch_bytes((int64_t)L + 1)));
+      GC_TRY(exclusive_scan(flag, pos, L, g->ws.take<char>(scan_scratch_bytes((int64_t)L + 1)), s));
+      k_compact_list<<<grid_for(L, 256, 2048), 256, 0, s>>>(list, L, flag, pos, sup, list2,
+                                                            misc + 2);
+      GC_LAUNCH_CHECK();
+      { int32_t *t = list; list = list2; list2 = t; }
+      L = alive;
     }
-    k_collect_flags<<<gsz(L), 256, 0, s>>>(list, L, thr, sup, flag);
+    // the level's first frontier: live edges with support < k - 2 (at least
+    // the edge of minimum support)
+    k_collect_flags<<<gsz(L), 256, 0, s>>>(list, L, thr, state, sup, flag);
     GC_LAUNCH_CHECK();
     GC_TRY(g->ws.reserve(scan_scratch_bytes((int64_t)L + 1)));
     GC_TRY(exclusive_scan(flag, pos, L, g->ws.take<char>(scan_scratch_bytes((int64_t)L + 1)), s));
@@ -570,16 +613,14 @@ gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStre
     GC_LAUNCH_CHECK();
     k_level_start<<<1, 64, 0, s>>>(ctl->cnt, pos + L);
     GC_LAUNCH_CHECK();
-    int32_t nfront = 0;
-    GC_HIP(hipMemcpyAsync(&nfront, pos + L, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    GC_HIP(hipStreamSynchronize(s));
-    if (nfront == 0) continue;
     ++stats[0];
     kmax = k - 1 > kmax ? k - 1 : kmax;
+    int64_t live = alive;  // live edges at the level start (or last compaction)
     // ---- rounds of level k, queued in batches without waiting for their
     // sizes (a round whose frontier is empty does nothing); the host looks at
     // the counters between batches, to stop and to compact ----
     int r = 0, batch = 1;
+    int32_t nfront = 0;
     for (;;) {
       for (int i = 0; i < batch; ++i, ++r) {
         int32_t *fr = buf[r & 1], *nx = buf[(r + 1) & 1];
@@ -593,13 +634,14 @@ gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStre
       GC_HIP(hipStreamSynchronize(s));
       nfront = h_ctl.cnt[r % 3];
       if (nfront == 0) break;
-      if ((L - (h_ctl.st[1] - removed_base)) * 2 < (int64_t)c.m) {
+      if ((live - (h_ctl.st[1] - removed_base)) * 2 < (int64_t)c.m) {
         GC_TRY(compact_peel(g, ps, c, next_store, buf[r & 1], nfront, s));
         sup = static_cast<int32_t *>(ps.sup[ps.cur].ptr);
         state = static_cast<uint8_t *>(ps.state[ps.cur].ptr);
         k_iota<<<gsz(c.m), 256, 0, s>>>(list, c.m);
         GC_LAUNCH_CHECK();
         L = c.m;
+        live = c.m;
         removed_base = h_ctl.st[1];
       }
       batch = batch < 16 ? batch * 2 : 16;
