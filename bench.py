@@ -369,7 +369,8 @@ def bench_serve(gc, n_graphs: int, n_requests: int, big_max: int, budget: int) -
         for i in range(len(reqs)):
             res[i] = srv.wait(tickets[i])
         wall = time.monotonic() - t0
-        lat = np.array([r["t_done"] - r["t_submit"] for r in res])
+        # latency percentiles over the requests after a warm-up tenth
+        lat = np.array([r["t_done"] - r["t_submit"] for r in res[len(res) // 10:]])
         edges = sum(r["edges"] for r in res)
         return res, wall, lat, edges
 
@@ -403,7 +404,8 @@ def bench_serve(gc, n_graphs: int, n_requests: int, big_max: int, budget: int) -
                                 "max_batch": stats0["max_batch"], "batches": stats0["batches"]},
         "exact_agreement": True,
         "workload": "R-MAT ef 16 pool, scale 10..14 (p=0.9) / 15..%d; 50%% triangle count, "
-                    "50%% 4-truss size; Poisson arrivals at 0.7 x per-call capacity" % big_max,
+                    "50%% 4-truss size; Poisson arrivals at 0.7 x per-call capacity; "
+                    "latency percentiles over the requests after the first tenth" % big_max,
     }
 
 
@@ -425,13 +427,13 @@ def main():
                     help="step = build + count only")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the per-bin strategy autotuner (run before the timed steps)")
-    ap.add_argument("--batch-graphs", type=int, default=512,
+    ap.add_argument("--batch-graphs", type=int, default=4096,
                     help="graphs in the batched-path comparison (0: skip)")
-    ap.add_argument("--batch-max-scale", type=int, default=14)
-    ap.add_argument("--serve-requests", type=int, default=2000,
+    ap.add_argument("--batch-max-scale", type=int, default=16)
+    ap.add_argument("--serve-requests", type=int, default=5000,
                     help="requests in the serving comparison (0: skip)")
-    ap.add_argument("--serve-graphs", type=int, default=128)
-    ap.add_argument("--serve-big-max", type=int, default=17)
+    ap.add_argument("--serve-graphs", type=int, default=512)
+    ap.add_argument("--serve-big-max", type=int, default=20)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one elementwise int32 kernel over 1 GiB (reads 1 GiB, "
                          "writes 1 GiB) so HBM counters can be scaled against known bytes")

@@ -1,0 +1,83 @@
+"""bench.py's host-side accounting, on the CPU: the algorithmic byte counts
+behind the roofline figure, checked against brute-force definitions on small
+graphs, and the one-GPU contract of the command line."""
+import itertools
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+import graphgen as gg
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def oriented(n, u, v):
+    """Degree-ordered orientation, rank = position in (deg, id) order."""
+    deg = np.bincount(u, minlength=n) + np.bincount(v, minlength=n)
+    order = np.lexsort((np.arange(n), deg))
+    rank = np.empty(n, np.int64)
+    rank[order] = np.arange(n)
+    a = np.minimum(rank[u], rank[v])
+    b = np.maximum(rank[u], rank[v])
+    o = np.lexsort((b, a))
+    a, b = a[o], b[o]
+    row_ptr = np.concatenate([[0], np.cumsum(np.bincount(a, minlength=n))]).astype(np.int32)
+    return row_ptr, b.astype(np.int32)
+
+
+def brute(n, row_ptr, col, chunk):
+    out = {a: list(col[row_ptr[a]:row_ptr[a + 1]]) for a in range(n)}
+    dout = {a: len(out[a]) for a in range(n)}
+    din = {x: 0 for x in range(n)}
+    for a in range(n):
+        for b in out[a]:
+            din[b] += 1
+    s_src = sum(d * d for d in dout.values())
+    s_dst = sum(dout[b] for a in range(n) for b in out[a])
+    # tail elements streamed: for every in-edge a -> b whose head has out-edges,
+    # the entries of N+(a) after b
+    probes = sum(1 for a in range(n) for i, b in enumerate(out[a]) if dout[b] > 0
+                 for _ in out[a][i + 1:])
+    in_edges = sum(1 for a in range(n) for b in out[a] if dout[b] > 0)
+    units = sum(-(-din[b] // chunk) for b in range(n) if dout[b] > 0 and din[b] > 0)
+    staged = sum(-(-din[b] // chunk) * dout[b] for b in range(n) if dout[b] > 0 and din[b] > 0)
+    m = len(col)
+    return {"S_src": s_src, "S_dst": s_dst, "probes": probes, "in_edges": in_edges,
+            "units": units, "staged": staged,
+            "B_model_min": min(16 * n + 20 * m + 4 * s_dst, 16 * n + 24 * m + 4 * s_src),
+            "bytes": 4 * probes + 8 * in_edges + 4 * staged + 24 * units}
+
+
+def test_algorithmic_bytes_match_brute_force():
+    for (src, dst, n), chunk in ((gg.rmat(8, 16, seed=3), 128), (gg.rmat(9, 8, seed=4), 4),
+                                 (gg.complete(40), 8), (gg.king(12), 128), (gg.star(50), 16)):
+        u, v = oracle.normalise(src, dst, n)
+        row_ptr, col = oriented(n, u, v)
+        got = bench.algorithmic_bytes(row_ptr, col, chunk=chunk)
+        want = brute(n, row_ptr, col, chunk)
+        for k, w in want.items():
+            assert got[k] == w, (k, got[k], w)
+
+
+def test_tail_probes_count_the_wedges_once():
+    """Every wedge a -> b, a -> c with b < c (both out of a) is one streamed
+    element when b has out-edges: on K_n that is C(n, 3) minus the wedges
+    whose middle is the last vertex."""
+    n = 30
+    u, v = oracle.normalise(*gg.complete(n)[:2], n)
+    row_ptr, col = oriented(n, u, v)
+    got = bench.algorithmic_bytes(row_ptr, col)
+    wedges = sum(1 for _ in itertools.combinations(range(n), 3))
+    assert got["probes"] == wedges  # every middle b < c has an out-edge to c
+
+
+def test_bench_refuses_more_than_one_gpu():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
