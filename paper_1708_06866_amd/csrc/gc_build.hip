@@ -143,8 +143,7 @@ __global__ void k_in_keys(const int32_t *__restrict__ col, int64_t m, uint64_t *
 __global__ void k_in_fill(const uint64_t *__restrict__ heads, const uint32_t *__restrict__ slots,
                           int64_t m, const int32_t *__restrict__ src,
                           const int32_t *__restrict__ row_ptr, int2 *__restrict__ in_tail,
-                          int32_t *__restrict__ in_slot, int32_t *__restrict__ in_src,
-                          int32_t *__restrict__ indeg) {
+                          int2 *__restrict__ in_edge, int32_t *__restrict__ indeg) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t span = (m + stride - 1) / stride * stride;
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < span; j += stride) {
@@ -153,9 +152,9 @@ __global__ void k_in_fill(const uint64_t *__restrict__ heads, const uint32_t *__
     if (valid) {
       const int32_t p = (int32_t)slots[j];
       x = (int32_t)heads[j];
-      in_slot[j] = p;
-      in_src[j] = src[p];
-      in_tail[j] = make_int2(p + 1, row_ptr[src[p] + 1]);
+      const int32_t a = src[p];
+      in_edge[j] = make_int2(a, p);
+      in_tail[j] = make_int2(p + 1, row_ptr[a + 1]);
     }
     wave_run_count(valid, x, indeg);
   }
@@ -168,8 +167,7 @@ gc_status build_in_lists(int32_t n, int32_t m, int bits, CsrStore &c, Workspace 
                          hipStream_t s) {
   GC_TRY(dalloc(c.in_ptr, sizeof(int32_t) * ((size_t)n + 1)));
   GC_TRY(dalloc(c.in_tail, sizeof(int2) * ((size_t)m + 1)));
-  GC_TRY(dalloc(c.in_slot, sizeof(int32_t) * ((size_t)m + 1)));
-  GC_TRY(dalloc(c.in_src, sizeof(int32_t) * ((size_t)m + 1)));
+  GC_TRY(dalloc(c.in_edge, sizeof(int2) * ((size_t)m + 1)));
   int32_t *in_ptr = static_cast<int32_t *>(c.in_ptr.ptr);
   GC_HIP(hipMemsetAsync(in_ptr, 0, sizeof(int32_t) * ((size_t)n + 1), s));
   if (m == 0) return GC_OK;
@@ -189,8 +187,7 @@ gc_status build_in_lists(int32_t n, int32_t m, int bits, CsrStore &c, Workspace 
   k_in_fill<<<gsz(m), BLK, 0, s>>>(ks, vs, m, static_cast<const int32_t *>(c.src.ptr),
                                    static_cast<const int32_t *>(c.row_ptr.ptr),
                                    static_cast<int2 *>(c.in_tail.ptr),
-                                   static_cast<int32_t *>(c.in_slot.ptr),
-                                   static_cast<int32_t *>(c.in_src.ptr), in_ptr);
+                                   static_cast<int2 *>(c.in_edge.ptr), in_ptr);
   GC_LAUNCH_CHECK();
   GC_TRY(exclusive_scan(in_ptr, in_ptr, n, cscr, s));
   return GC_OK;

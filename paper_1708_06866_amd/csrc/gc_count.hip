@@ -656,7 +656,7 @@ __global__ __launch_bounds__(CBLK) void k_sup_lds(CsrView c, const int4 *__restr
         }
         if (nx.j != it.j) {  // the in-edge is complete
           const int32_t tot = wave_sum_i32(mine);
-          if (lane == 0 && tot) atomicAdd(&sup[c.in_slot[it.j]], tot);
+          if (lane == 0 && tot) atomicAdd(&sup[c.in_edge[it.j].y], tot);
           mine = 0;
         }
         if (nx.j >= j1) break;
@@ -695,7 +695,7 @@ __global__ __launch_bounds__(CBLK) void k_sup_search(CsrView c, const int4 *__re
         }
       }
       const int32_t tot = wave_sum_i32(mine);
-      if (lane == 0 && tot) atomicAdd(&sup[c.in_slot[j]], tot);
+      if (lane == 0 && tot) atomicAdd(&sup[c.in_edge[j].y], tot);
     }
   }
 }

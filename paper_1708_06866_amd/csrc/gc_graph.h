@@ -10,8 +10,8 @@ namespace gc {
 // vertex" schedule walks.  For oriented slot p (edge r -> col[p], r = src[p]):
 //   tail(p) = [p + 1, row_ptr[r + 1])   the part of N+(r) above col[p]
 // and the in-list of vertex x lists, for every slot p with col[p] = x, the
-// range tail(p) packed as int2 {p + 1, row_end}; in_slot[j] is p itself and
-// in_src[j] its source (in-lists are sorted by source).
+// range tail(p) packed as int2 {p + 1, row_end}, and in_edge[j] = {source
+// of p, p} (in-lists are sorted by source; key and slot share one load).
 struct CsrView {
   int32_t n = 0;
   int32_t m = 0;
@@ -21,14 +21,13 @@ struct CsrView {
   const int32_t *eid = nullptr;      // [m]
   const int32_t *in_ptr = nullptr;   // [n+1]
   const int2 *in_tail = nullptr;     // [m]
-  const int32_t *in_slot = nullptr;  // [m]
-  const int32_t *in_src = nullptr;   // [m]
+  const int2 *in_edge = nullptr;     // [m] {source, slot} of each in-edge
 };
 
 // Owned device arrays of one oriented CSR (base graph or a k-truss working
 // copy).
 struct CsrStore {
-  DeviceBuffer row_ptr, col, src, eid, in_ptr, in_tail, in_slot, in_src;
+  DeviceBuffer row_ptr, col, src, eid, in_ptr, in_tail, in_edge;
   CsrView view(int32_t n, int32_t m) const {
     CsrView v;
     v.n = n;
@@ -39,17 +38,16 @@ struct CsrStore {
     v.eid = static_cast<const int32_t *>(eid.ptr);
     v.in_ptr = static_cast<const int32_t *>(in_ptr.ptr);
     v.in_tail = static_cast<const int2 *>(in_tail.ptr);
-    v.in_slot = static_cast<const int32_t *>(in_slot.ptr);
-    v.in_src = static_cast<const int32_t *>(in_src.ptr);
+    v.in_edge = static_cast<const int2 *>(in_edge.ptr);
     return v;
   }
   void release() {
     dfree(row_ptr); dfree(col); dfree(src); dfree(eid);
-    dfree(in_ptr); dfree(in_tail); dfree(in_slot); dfree(in_src);
+    dfree(in_ptr); dfree(in_tail); dfree(in_edge);
   }
   size_t bytes() const {
     return row_ptr.bytes + col.bytes + src.bytes + eid.bytes + in_ptr.bytes +
-           in_tail.bytes + in_slot.bytes + in_src.bytes;
+           in_tail.bytes + in_edge.bytes;
   }
 };
 

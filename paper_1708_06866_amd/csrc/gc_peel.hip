@@ -72,20 +72,28 @@ __device__ __forceinline__ int destroy(bool found, int32_t p, int32_t q1, int32_
 
 constexpr int PEEL_U = 4;  // candidates per lane in flight
 
-// Searches of PEEL_U keys, each in its own sorted range arr[u][lo, hi), run in
-// lockstep so their loads overlap; out[u] = index of key[u] or -1 (also -1
-// where the range is empty).
-__device__ __forceinline__ void find_many(const int32_t *const (&arr)[PEEL_U],
-                                          const int32_t (&lo)[PEEL_U], const int32_t (&hi)[PEEL_U],
-                                          const int32_t (&key)[PEEL_U], int32_t (&out)[PEEL_U]) {
+// Keys of the two list layouts: a row holds the neighbour (its slot is the
+// position), an in-list entry holds {neighbour, slot}.
+__device__ __forceinline__ int32_t key_of(int32_t e) { return e; }
+__device__ __forceinline__ int32_t key_of(int2 e) { return e.x; }
+__device__ __forceinline__ int32_t slot_of(int32_t, int32_t pos) { return pos; }
+__device__ __forceinline__ int32_t slot_of(int2 e, int32_t) { return e.y; }
+
+// Searches of PEEL_U keys in one sorted list arr[lo, hi), run in lockstep so
+// their loads overlap; out[u] = slot of the edge holding key[u], or -1 (also
+// -1 where act[u] is false, which loads nothing).
+template <class T>
+__device__ __forceinline__ void find_many(const T *__restrict__ arr, int32_t lo, int32_t hi,
+                                          const int32_t (&key)[PEEL_U], const bool (&act)[PEEL_U],
+                                          int32_t (&out)[PEEL_U]) {
   int32_t l[PEEL_U], n[PEEL_U];
 #pragma unroll
-  for (int u = 0; u < PEEL_U; ++u) { l[u] = lo[u]; n[u] = hi[u] - lo[u]; }
+  for (int u = 0; u < PEEL_U; ++u) { l[u] = lo; n[u] = act[u] ? hi - lo : 0; }
   for (;;) {
     bool any = false;
     int32_t v[PEEL_U];
 #pragma unroll
-    for (int u = 0; u < PEEL_U; ++u) v[u] = n[u] > 0 ? arr[u][l[u] + (n[u] >> 1)] : 0;
+    for (int u = 0; u < PEEL_U; ++u) v[u] = n[u] > 0 ? key_of(arr[l[u] + (n[u] >> 1)]) : 0;
 #pragma unroll
     for (int u = 0; u < PEEL_U; ++u) {
       if (n[u] > 0) {
@@ -97,14 +105,21 @@ __device__ __forceinline__ void find_many(const int32_t *const (&arr)[PEEL_U],
     if (!any) break;
   }
 #pragma unroll
-  for (int u = 0; u < PEEL_U; ++u) out[u] = (l[u] < hi[u] && arr[u][l[u]] == key[u]) ? l[u] : -1;
+  for (int u = 0; u < PEEL_U; ++u) {
+    out[u] = -1;
+    if (act[u] && l[u] < hi) {
+      const T e = arr[l[u]];
+      if (key_of(e) == key[u]) out[u] = slot_of(e, l[u]);
+    }
+  }
 }
 
-__device__ __forceinline__ int32_t lower_bound_i32(const int32_t *__restrict__ a, int32_t lo,
-                                                   int32_t hi, int32_t key) {
+template <class T>
+__device__ __forceinline__ int32_t lower_bound_key(const T *__restrict__ a, int32_t lo, int32_t hi,
+                                                   int32_t key) {
   while (lo < hi) {
     const int32_t mid = lo + ((hi - lo) >> 1);
-    if (a[mid] < key) lo = mid + 1; else hi = mid;
+    if (key_of(a[mid]) < key) lo = mid + 1; else hi = mid;
   }
   return lo;
 }
@@ -121,13 +136,14 @@ __device__ __forceinline__ PeelEdge peel_edge(const CsrView &c, int32_t a, int32
   e.rb0 = c.row_ptr[b]; e.rb1 = c.row_ptr[b + 1];
   e.ia0 = c.in_ptr[a]; e.ia1 = c.in_ptr[a + 1];
   e.ib0 = c.in_ptr[b]; e.ib1 = c.in_ptr[b + 1];
-  e.ibA = lower_bound_i32(c.in_src, e.ib0, e.ib1, a);  // in_src[ibA] == a (edge p)
+  e.ibA = lower_bound_key(c.in_edge, e.ib0, e.ib1, a);  // in_edge[ibA] = {a, p}
   return e;
 }
 
 // One of the three intersections (see k_peel): iterate A[A0, A0 + nA), search
 // B[B0, B0 + nB); nA = 0 when either side is empty.  flags: bit 0 A is an
-// in-list, bit 1 B is an in-list, bit 2 A holds the edge between a and x.
+// in-list, bit 1 B is an in-list (entries {neighbour, slot} of in_edge; else a
+// stretch of col, slot = position).
 struct PeelCase {
   int32_t A0, nA, B0, nB;
   uint32_t flags;
@@ -135,24 +151,22 @@ struct PeelCase {
 
 __device__ __forceinline__ PeelCase peel_case(const PeelEdge &e, int32_t p, int cs) {
   int32_t A0, A1, B0, B1;
-  bool A_in, B_in;  // side is an in-list (keys in_src, slots in_slot) or a row
+  bool A_in, B_in;
   if (cs == 0) { A0 = p + 1; A1 = e.ra1; A_in = false; B0 = e.rb0; B1 = e.rb1; B_in = false; }
   else if (cs == 1) { A0 = e.ra0; A1 = p; A_in = false; B0 = e.ibA + 1; B1 = e.ib1; B_in = true; }
   else { A0 = e.ia0; A1 = e.ia1; A_in = true; B0 = e.ib0; B1 = e.ibA; B_in = true; }
-  bool a_is_ax = cs != 2;
   if (A1 - A0 > B1 - B0) {  // iterate the shorter side
     int32_t t;
     t = A0; A0 = B0; B0 = t;
     t = A1; A1 = B1; B1 = t;
     const bool tb = A_in; A_in = B_in; B_in = tb;
-    a_is_ax = !a_is_ax;
   }
   PeelCase pc;
   pc.A0 = A0;
   pc.B0 = B0;
   pc.nB = B1 - B0;
   pc.nA = (A1 - A0 > 0 && B1 - B0 > 0) ? A1 - A0 : 0;
-  pc.flags = (A_in ? 1u : 0u) | (B_in ? 2u : 0u) | (a_is_ax ? 4u : 0u);
+  pc.flags = (A_in ? 1u : 0u) | (B_in ? 2u : 0u);
   return pc;
 }
 
@@ -203,42 +217,43 @@ __global__ __launch_bounds__(PBLK) void k_peel(CsrView c, const int32_t *__restr
       const PeelCase pc = peel_case(e, p, cs);
       const int32_t nA = pc.nA, A0 = pc.A0, B0 = pc.B0, B1 = pc.B0 + pc.nB;
       if (nA == 0) continue;
-      const bool A_in = pc.flags & 1u, B_in = pc.flags & 2u, a_is_ax = pc.flags & 4u;
-      const int32_t *keysB = B_in ? c.in_src : c.col;
+      const bool A_in = pc.flags & 1u, B_in = pc.flags & 2u;
       for (int32_t t0 = sub * 64 + lane; t0 - lane < nA && !(wpe == 1 && seen >= need);
            t0 += stride * PEEL_U) {
-        int32_t qk[PEEL_U], key[PEEL_U], lo[PEEL_U], hi[PEEL_U], idx[PEEL_U];
+        int32_t qk[PEEL_U], key[PEEL_U], hit[PEEL_U];
+        bool act[PEEL_U];
 #pragma unroll
         for (int u = 0; u < PEEL_U; ++u) {
           const int32_t t = t0 + u * stride;
           qk[u] = -1;
           key[u] = 0;
-          lo[u] = 0;
-          hi[u] = 0;
+          act[u] = false;
           if (t < nA) {
             ++n_cand;
             const int32_t i = A0 + t;
-            const int32_t q = A_in ? c.in_slot[i] : i;
+            int32_t q, x;
+            if (A_in) {
+              const int2 ie = c.in_edge[i];
+              x = ie.x;
+              q = ie.y;
+            } else {
+              x = c.col[i];
+              q = i;
+            }
             if (state[q] != EDGE_DEAD) {
               qk[u] = q;
-              key[u] = A_in ? c.in_src[i] : c.col[i];
-              lo[u] = B0;
-              hi[u] = B1;
+              key[u] = x;
+              act[u] = true;
               ++n_search;
             }
           }
         }
-        const int32_t *arr[PEEL_U] = {keysB, keysB, keysB, keysB};
-        find_many(arr, lo, hi, key, idx);
+        if (B_in) find_many(c.in_edge, B0, B1, key, act, hit);
+        else find_many(c.col, B0, B1, key, act, hit);
 #pragma unroll
         for (int u = 0; u < PEEL_U; ++u) {
-          int32_t q1 = -1, q2 = -1;
-          if (qk[u] >= 0 && idx[u] >= 0) {
-            const int32_t other = B_in ? c.in_slot[idx[u]] : idx[u];
-            q1 = a_is_ax ? qk[u] : other;  // edge between a and x
-            q2 = a_is_ax ? other : qk[u];  // edge between b and x
-          }
-          const int r = destroy(q1 >= 0, p, q1, q2, thr, state, sup, next, next_count);
+          // q1, q2: the edges between x and the two ends of p (either order)
+          const int r = destroy(hit[u] >= 0, p, qk[u], hit[u], thr, state, sup, next, next_count);
           n_found += r & 1;
           n_ours += r >> 1;
           seen += __popcll(__ballot(r & 1));
