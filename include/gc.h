@@ -132,6 +132,9 @@ gc_status gc_ktruss(gc_graph *g, int32_t k, uint8_t *d_in_truss, int64_t cap,
  *   2 binary search in the sorted row in HBM (the only one for the last bin)
  *   3 bucketed LDS hash table (4 slots per 16-byte bucket), load <= 1/2
  *   4 bucketed LDS hash table, load <= 1/4
+ *   5 a group of lanes per work unit (16 in bin 0, a wavefront in bin 1)
+ *     with its own LDS table, one lane per in-edge (bins 0 and 1 only: many
+ *     small units)
  * Results never depend on the strategy.  A new handle takes them from the
  * file named by the environment variable GC_AUTOTUNE_CACHE if it exists
  * (lines "<arch> <bin> <strategy>"), else {0, 0, 0, 0, 2}. */
@@ -139,7 +142,8 @@ gc_status gc_ktruss(gc_graph *g, int32_t k, uint8_t *d_in_truss, int64_t cap,
 /* Autotuner: time every admissible strategy of every bin that has work on
  * this graph (HIP events, first run discarded), keep the fastest per bin and,
  * if GC_AUTOTUNE_CACHE is set, write the choices there.  h_strategy[5] and
- * h_ms[5*5] (mean ms per bin and strategy, -1 where not run) may be NULL.
+ * h_ms[5*6] (mean ms per bin and strategy, row-major by bin; -1 where not
+ * run) may be NULL.
  * Synchronises `stream`. */
 gc_status gc_graph_autotune(gc_graph *g, gc_stream stream, int32_t *h_strategy,
                             float *h_ms);
@@ -215,7 +219,7 @@ gc_status gc_batch_ktruss(gc_batch *b, int32_t k, uint8_t *d_mask, int64_t cap,
 /* Autotuner of a batch, as gc_graph_autotune (strategies listed there):
  * times every admissible count strategy per degree bin on the whole batch,
  * keeps the fastest, writes GC_AUTOTUNE_CACHE if set.  h_strategy[5] and
- * h_ms[5*5] may be NULL.  Results never depend on the choice. */
+ * h_ms[5*6] may be NULL.  Results never depend on the choice. */
 gc_status gc_batch_autotune(gc_batch *b, gc_stream stream, int32_t *h_strategy,
                             float *h_ms);
 

@@ -42,6 +42,10 @@ GC_FILE_MMIO = 2
 
 GC_PENDING = 1
 
+# count strategies: N_BINS degree bins, N_STRATEGIES strategies (include/gc.h)
+N_BINS = 5
+N_STRATEGIES = 6
+
 _lib = None
 
 
@@ -217,14 +221,14 @@ class Graph:
         return gc_truss_decomposition(self, out, stream)
 
     def autotune(self, stream=None):
-        """Per-bin count strategies chosen by timing: (strategy[5], ms[5, 5])."""
+        """Per-bin count strategies chosen by timing: (strategy[5], ms[5, 6])."""
         import numpy as np
         st = np.zeros(5, dtype=np.int32)
-        ms = np.zeros(25, dtype=np.float32)
+        ms = np.zeros(N_BINS * N_STRATEGIES, dtype=np.float32)
         _check(lib().gc_graph_autotune(self.handle, _stream(stream),
                                        ctypes.c_void_p(st.ctypes.data),
                                        ctypes.c_void_p(ms.ctypes.data)), "gc_graph_autotune")
-        return st, ms.reshape(5, 5)
+        return st, ms.reshape(N_BINS, N_STRATEGIES)
 
     def truss_stats(self) -> dict:
         """Counters of the last truss decomposition on this handle."""
@@ -428,11 +432,11 @@ class Batch:
         return mask[:m], mk[:self.n_graphs]
 
     def autotune(self, stream=None):
-        st = _np.zeros(5, dtype=_np.int32)
-        ms = _np.zeros(25, dtype=_np.float32)
+        st = _np.zeros(N_BINS, dtype=_np.int32)
+        ms = _np.zeros(N_BINS * N_STRATEGIES, dtype=_np.float32)
         _check(lib().gc_batch_autotune(self.handle, _stream(stream), ctypes.c_void_p(st.ctypes.data),
                                        ctypes.c_void_p(ms.ctypes.data)), "gc_batch_autotune")
-        return st, ms.reshape(5, 5)
+        return st, ms.reshape(N_BINS, N_STRATEGIES)
 
     def set_strategy(self, strategy):
         st = _np.ascontiguousarray(strategy, dtype=_np.int32)

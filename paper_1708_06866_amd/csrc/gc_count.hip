@@ -319,6 +319,72 @@ __global__ __launch_bounds__(CBLK) void k_tc_lds(CsrView c, const int4 *__restri
   if (!out.per_graph && lane == 0 && total) atomicAdd(out.total, total);
 }
 
+// Make this wave's LDS stores visible to its other lanes (and its loads done
+// before later stores): within one wave a fence and a wave barrier suffice.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Short out-lists (strategy 5): a group of GL lanes per unit with a table of
+// its own in LDS, so there are no block barriers; lane l of the group takes
+// the unit's in-edges first + l, first + l + GL, ... and walks each tail on
+// its own.  Suits graphs whose units are many and small (tails of a few
+// elements, as in sparse uniform graphs), where a block per unit would mostly
+// wait at barriers.  The lanes of a group always hold the same unit, so they
+// stay converged; groups of one wave may be at different units (each only
+// touches its own table).
+template <int LOGS, int GL>
+__global__ __launch_bounds__(CBLK) void k_tc_group(CsrView c, const int4 *__restrict__ units,
+                                                   int64_t nunits, CountOut out) {
+  using TB = LinTable<LOGS>;
+  constexpr int GPB = CBLK / GL;  // groups per block
+  __shared__ int32_t tabs[GPB][TB::SLOTS];
+  const int gl = threadIdx.x % GL;
+  int32_t *tab = tabs[threadIdx.x / GL];
+  const int64_t gid = ((int64_t)blockIdx.x * CBLK + threadIdx.x) / GL;
+  const int64_t ng = (int64_t)gridDim.x * GPB;
+  int32_t hits = 0;  // over every unit of this lane (total count)
+  for (int64_t ui = gid; ui < nunits; ui += ng) {
+    const int4 U = units[ui];
+    const int32_t rb = c.row_ptr[U.x], re = c.row_ptr[U.x + 1];
+    for (int i = gl; i < TB::SLOTS; i += GL) tab[i] = -1;
+    wave_lds_sync();
+    for (int32_t i = rb + gl; i < re; i += GL) TB::insert(tab, c.col[i]);
+    wave_lds_sync();
+    int32_t mine = 0;
+    for (int32_t j = U.y + gl; j < U.z; j += GL) {
+      const int2 t = c.in_tail[j];
+      int32_t p = t.x;
+      for (; p + 4 <= t.y; p += 4) {
+        int32_t w[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) w[u] = c.col[p + u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) mine += TB::find(tab, w[u], TB::first(tab, w[u])) >= 0;
+      }
+      for (; p < t.y; ++p) {
+        const int32_t w = c.col[p];
+        mine += TB::find(tab, w, TB::first(tab, w)) >= 0;
+      }
+    }
+    if (out.per_graph) {
+      // sum over the group (its lanes are converged) and one atomic per unit
+      for (int o = GL / 2; o > 0; o >>= 1) mine += __shfl_xor(mine, o, GL);
+      if (gl == 0 && mine)
+        atomicAdd(&out.per_graph[out.graph_of_rank[U.x]], (unsigned long long)mine);
+    } else {
+      hits += mine;
+    }
+    wave_lds_sync();  // the group is done with the table before it is cleared
+  }
+  if (!out.per_graph) {
+    const int32_t sum = wave_sum_i32(hits);  // all lanes are back together here
+    if ((threadIdx.x & 63) == 0 && sum) atomicAdd(out.total, (unsigned long long)sum);
+  }
+}
+
 // Out-lists too long for LDS: binary search in the sorted row in HBM.
 __global__ __launch_bounds__(CBLK) void k_tc_search(CsrView c, const int4 *__restrict__ units,
                                                     int64_t nunits, CountOut out) {
@@ -359,10 +425,12 @@ static unsigned unit_grid(int64_t nunits, int per_cu) {
 // Strategies per bin (the autotuner's search space):
 //   0 linear-probing table, load <= 1/2     1 linear-probing table, load <= 1/4
 //   2 binary search in HBM                  3 bucketed table, load <= 1/2
-//   4 bucketed table, load <= 1/4
+//   4 bucketed table, load <= 1/4           5 one wave per unit, own table
+//                                             (bins 0 and 1 only)
 // The last (unbounded) bin only admits 2.
 bool count_strategy_valid(int bin, int strategy) {
   if (strategy == 2) return true;
+  if (strategy == 5) return bin <= 1;
   return bin < NBINS - 1 && strategy >= 0 && strategy < kCountStrategies;
 }
 
@@ -383,6 +451,11 @@ static gc_status launch_count_bin(const CsrView &c, const int4 *ub, int64_t nu, 
                                   int strategy, const CountOut &o, hipStream_t s) {
   if (strategy == 2 || b == NBINS - 1) {
     k_tc_search<<<unit_grid(nu, 8), CBLK, 0, s>>>(c, ub, nu, o);
+  } else if (strategy == 5) {
+    if (b == 0)  // d+ <= 32: groups of 16 lanes, 16 units per block
+      k_tc_group<6, 16><<<unit_grid((nu + 15) / 16, 16), CBLK, 0, s>>>(c, ub, nu, o);
+    else         // d+ <= 256: a wave per unit
+      k_tc_group<9, 64><<<unit_grid((nu + 3) / 4, 16), CBLK, 0, s>>>(c, ub, nu, o);
   } else if (strategy == 0 || strategy == 1) {
     switch (bin_logs_count(b) + (strategy == 1 ? 1 : 0)) {
       case 6: launch_tc_lds<LinTable<6>>(c, ub, nu, o, s); break;

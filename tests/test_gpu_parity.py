@@ -386,11 +386,12 @@ def test_decomposition_peel_equals_rounds(monkeypatch):
 
 
 @pytest.mark.parametrize("strategy", [[0, 0, 0, 0, 2], [1, 1, 1, 1, 2], [2, 2, 2, 2, 2],
-                                      [3, 3, 3, 3, 2], [4, 4, 4, 4, 2]])
+                                      [3, 3, 3, 3, 2], [4, 4, 4, 4, 2], [5, 5, 0, 0, 2]])
 def test_count_strategies_agree(strategy):
     """Every count strategy gives the oracle's count (bins 0-3 exercised by the
     R-MAT graph and a complete graph reaching d+ > 2048)."""
-    for src, dst, n in (gg.rmat(14, 16, seed=2), gg.complete(2300)):
+    for src, dst, n in (gg.rmat(14, 16, seed=2), gg.complete(2300),
+                        gg.er(1 << 15, 16 << 15, seed=5)):
         g = gc.build_graph(src, dst, n)
         g.set_strategy(strategy)
         u, v = oracle.normalise(src, dst, n)
@@ -409,6 +410,8 @@ def test_autotune_keeps_counts():
     assert st[4] == 2 and g.triangle_count() == T
     with pytest.raises(gc.GCError):
         g.set_strategy([0, 0, 0, 0, 1])
+    with pytest.raises(gc.GCError):
+        g.set_strategy([0, 0, 5, 0, 2])   # one wave per unit only for bins 0 and 1
     g.free()
 
 
