@@ -745,6 +745,54 @@ __global__ __launch_bounds__(CBLK) void k_sup_lds(CsrView c, const int4 *__restr
   }
 }
 
+// Short out-lists: a group of GL lanes per unit, as k_tc_group, each with its
+// own table, staged-edge slots and counters in LDS; lane l of the group takes
+// in-edges first + l, first + l + GL, ... and adds its hits to that in-edge
+// once.
+template <int LOGS, int GL>
+__global__ __launch_bounds__(CBLK) void k_sup_group(CsrView c, const int4 *__restrict__ units,
+                                                    int64_t nunits, int32_t *__restrict__ sup) {
+  using TB = LinTable<LOGS>;
+  constexpr int NS = TB::SLOTS;
+  constexpr int GPB = CBLK / GL;  // groups per block
+  __shared__ int32_t tabs[GPB][NS];
+  __shared__ int32_t slots[GPB][NS];  // oriented slot of the staged edge b -> c
+  __shared__ int32_t cnts[GPB][NS];   // hits on that edge within this unit
+  const int gl = threadIdx.x % GL, grp = threadIdx.x / GL;
+  int32_t *tab = tabs[grp], *tslot = slots[grp], *tcnt = cnts[grp];
+  const int64_t gid = ((int64_t)blockIdx.x * CBLK + threadIdx.x) / GL;
+  const int64_t ng = (int64_t)gridDim.x * GPB;
+  for (int64_t ui = gid; ui < nunits; ui += ng) {
+    const int4 U = units[ui];
+    const int32_t rb = c.row_ptr[U.x], re = c.row_ptr[U.x + 1];
+    for (int i = gl; i < NS; i += GL) {
+      tab[i] = -1;
+      tcnt[i] = 0;
+    }
+    wave_lds_sync();
+    for (int32_t i = rb + gl; i < re; i += GL) tslot[TB::insert(tab, c.col[i])] = i;
+    wave_lds_sync();
+    for (int32_t j = U.y + gl; j < U.z; j += GL) {
+      const int2 t = c.in_tail[j];
+      int32_t mine = 0;  // hits of in-edge j (edge a -> b)
+      for (int32_t p = t.x; p < t.y; ++p) {
+        const int32_t w = c.col[p];
+        const int32_t at = TB::find(tab, w, TB::first(tab, w));
+        if (at >= 0) {
+          ++mine;
+          atomicAdd(&tcnt[at], 1);  // edge b -> c
+          atomicAdd(&sup[p], 1);    // edge a -> c
+        }
+      }
+      if (mine) atomicAdd(&sup[c.in_edge[j].y], mine);
+    }
+    wave_lds_sync();
+    for (int i = gl; i < NS; i += GL)
+      if (tcnt[i]) atomicAdd(&sup[tslot[i]], tcnt[i]);
+    wave_lds_sync();  // the group is done with its arrays before they are cleared
+  }
+}
+
 __global__ __launch_bounds__(CBLK) void k_sup_search(CsrView c, const int4 *__restrict__ units,
                                                      int64_t nunits, int32_t *__restrict__ sup) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -780,7 +828,7 @@ gc_status slot_support(const CsrView &c, const UnitStore &u, int32_t *d_sup, hip
     if (nu == 0) continue;
     const int4 *ub = units + u.bin_begin[b];
     switch (b) {
-      case 0: k_sup_lds<6><<<unit_grid(nu, 16), CBLK, 0, s>>>(c, ub, nu, d_sup); break;
+      case 0: k_sup_group<6, 16><<<unit_grid((nu + 15) / 16, 16), CBLK, 0, s>>>(c, ub, nu, d_sup); break;
       case 1: k_sup_lds<9><<<unit_grid(nu, 16), CBLK, 0, s>>>(c, ub, nu, d_sup); break;
       case 2: k_sup_lds<12><<<unit_grid(nu, 4), CBLK, 0, s>>>(c, ub, nu, d_sup); break;
       case 3: k_sup_lds<13><<<unit_grid(nu, 2), CBLK, 0, s>>>(c, ub, nu, d_sup); break;
