@@ -116,11 +116,15 @@ gc_status gc_edge_support(gc_graph *g, int32_t *d_support, int64_t cap,
                           gc_stream stream);
 
 /* k-truss (Sec. III-B, Alg. 4): d_in_truss[e] = 1 if canonical edge e belongs
- * to the maximal k-truss, else 0 (device, uint8, m entries).  Edges are
- * removed in rounds: support is recomputed on the remaining edges, every edge
- * with support < k-2 is dropped, and the edge list is compacted, until no
- * edge is dropped.  *h_m_k (host, may be NULL) receives the number of edges in
- * the k-truss.  k < 2 gives GC_EINVAL; k = 2 keeps every edge.
+ * to the maximal k-truss, else 0 (device, uint8, m entries).  The result is
+ * the fixed point of Alg. 4 (drop every edge with support < k-2 until none
+ * is dropped); it is reached by peeling: support is counted once, and the
+ * levels 3 .. k of the truss decomposition remove edges in rounds while the
+ * support of the survivors is decremented per destroyed triangle.  With the
+ * environment variable GC_TRUSS_METHOD=rounds, Alg. 4's own rounds are run
+ * instead (support recounted on the compacted remaining edges each round);
+ * both give the same set.  *h_m_k (host, may be NULL) receives the number of
+ * edges in the k-truss.  k < 2 gives GC_EINVAL; k = 2 keeps every edge.
  * Synchronises `stream`. */
 gc_status gc_ktruss(gc_graph *g, int32_t k, uint8_t *d_in_truss, int64_t cap,
                     gc_stream stream, int64_t *h_m_k);

@@ -145,7 +145,11 @@ struct GraphDesc {
 gc_status count_multi_launch(const GraphDesc *d_desc, const int64_t *d_pre, const int64_t *h_pre,
                              int32_t nh, unsigned long long *d_out, hipStream_t s);
 // (gc_peel.hip) truss numbers by peeling with incremental support updates;
-// tau must hold m entries.
-gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStream_t s);
+// tau holds m entries, or is null (truss numbers not written).  With k_stop,
+// peeling ends before the first level above k_stop: mask (m bytes, may be
+// null) then marks the edges of the k_stop-truss and *h_mk counts them.
+gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStream_t s,
+                             int32_t k_stop = 0x7fffffff, uint8_t *mask = nullptr,
+                             int64_t *h_mk = nullptr);
 
 }  // namespace gc

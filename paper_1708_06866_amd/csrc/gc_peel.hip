@@ -301,7 +301,7 @@ __global__ void k_advance(const int32_t *__restrict__ front, const int32_t *__re
     if (i < nfront) {
       const int32_t p = front[i];
       state[p] = EDGE_DEAD;
-      tau[eid[p]] = tau_val;
+      if (tau) tau[eid[p]] = tau_val;
     }
   }
   // the next frontier is disjoint from the current one (its edges were alive
@@ -417,6 +417,14 @@ __global__ void k_collect_scatter(const int32_t *__restrict__ list, int32_t L,
     }
 }
 
+// mask[eid[p]] = 1 for every slot p whose edge is not dead
+__global__ void k_mask_live(const uint8_t *__restrict__ state, const int32_t *__restrict__ eid,
+                            int32_t m, uint8_t *__restrict__ mask) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+       i += (int64_t)gridDim.x * blockDim.x)
+    if (state[i] != EDGE_DEAD) mask[eid[i]] = 1;
+}
+
 __global__ void k_iota(int32_t *__restrict__ x, int32_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -521,8 +529,11 @@ static gc_status compact_peel(gc_graph *g, PeelState &ps, CsrView &c, int &next,
   return GC_OK;
 }
 
-gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStream_t s) {
+gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStream_t s,
+                             int32_t k_stop, uint8_t *mask, int64_t *h_mk) {
   const int32_t m = (int32_t)g->m;
+  if (mask && m > 0) GC_HIP(hipMemsetAsync(mask, 0, (size_t)m, s));
+  if (h_mk) *h_mk = 0;
   if (m == 0) {
     if (h_kmax) *h_kmax = 0;
     return GC_OK;
@@ -598,6 +609,15 @@ gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStre
     if (alive == 0) break;
     const int32_t k = h[0] + 3;   // first level that removes something
     const int32_t thr = k - 2;
+    if (k > k_stop) {
+      // every live edge survives the levels up to k_stop: the k_stop-truss
+      if (mask) {
+        k_mask_live<<<grid_for(c.m, 256, 4096), 256, 0, s>>>(state, c.eid, c.m, mask);
+        GC_LAUNCH_CHECK();
+      }
+      if (h_mk) *h_mk = alive;
+      break;
+    }
     if ((int64_t)alive * 2 < (int64_t)c.m) {
       // compact the CSR when at least half of it is dead
       GC_TRY(compact_peel(g, ps, c, next_store, buf[0], 0, s));

@@ -241,7 +241,19 @@ extern "C" gc_status gc_ktruss(gc_graph *g, int32_t k, uint8_t *d_in_truss, int6
   int prev = 0;
   GC_HIP(hipGetDevice(&prev));
   if (prev != g->device) GC_HIP(hipSetDevice(g->device));
-  gc_status st = ktruss_impl(g, k, d_in_truss, h_m_k, static_cast<hipStream_t>(stream));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  gc_status st;
+  const char *method = getenv("GC_TRUSS_METHOD");
+  if (k <= 2 || (method && strcmp(method, "rounds") == 0)) {
+    st = ktruss_impl(g, k, d_in_truss, h_m_k, s);
+  } else {
+    // the k-truss is what survives the peeling levels 3 .. k
+    st = decomposition_peel(g, nullptr, nullptr, s, k, d_in_truss, h_m_k);
+    if (st == GC_OK && hipStreamSynchronize(s) != hipSuccess) {
+      set_error("gc_ktruss: stream synchronize failed");
+      st = GC_EDEVICE;
+    }
+  }
   if (prev != g->device) (void)hipSetDevice(prev);
   return st;
 }

@@ -385,6 +385,26 @@ def test_decomposition_peel_equals_rounds(monkeypatch):
         g.free()
 
 
+def test_ktruss_peel_equals_rounds(monkeypatch):
+    """k-truss by peeling the levels 3 .. k and by Alg. 4's recount rounds give
+    the same edge set and size, and both match the oracle's truss numbers."""
+    for label, (src, dst, n) in (("rmat14", gg.rmat(14, 16, seed=7)),
+                                 ("rgg12", gg.rgg(1 << 12, 20.0, seed=8)),
+                                 ("K30", gg.complete(30)), ("star", gg.star(40))):
+        say("case ktruss methods", label)
+        g = gc.build_graph(src, dst, n)
+        u, v = oracle.normalise(src, dst, n)
+        tau_ref, kmax = oracle.truss_decomposition(n, u, v, "peel")
+        for k in sorted(set([2, 3, 4, 5, kmax - 1, kmax, kmax + 1, kmax + 5]) - {0, 1}):
+            ref = (tau_ref >= k).astype(np.uint8)
+            for method in ("rounds", "peel"):
+                monkeypatch.setenv("GC_TRUSS_METHOD", method)
+                mask, mk = g.ktruss(k)
+                assert np.array_equal(mask.cpu().numpy(), ref), (label, k, method)
+                assert mk == int(ref.sum()), (label, k, method)
+        g.free()
+
+
 @pytest.mark.parametrize("strategy", [[0, 0, 0, 0, 2], [1, 1, 1, 1, 2], [2, 2, 2, 2, 2],
                                       [3, 3, 3, 3, 2], [4, 4, 4, 4, 2], [5, 5, 0, 0, 2]])
 def test_count_strategies_agree(strategy):
