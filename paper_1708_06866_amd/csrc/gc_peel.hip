@@ -170,6 +170,83 @@ __device__ __forceinline__ PeelCase peel_case(const PeelEdge &e, int32_t p, int 
   return pc;
 }
 
+// Lane-balanced batches (large frontiers): a wave takes up to 64 frontier
+// edges at once, lays their candidates end to end (edge by edge, case by case)
+// and gives each lane the next candidate of that concatenation, so a batch of
+// short lists keeps every lane busy.  The batch lives in LDS, one per wave.
+struct PeelBatch {
+  long long off[64];  // first candidate of edge e in the concatenation
+  int32_t p[64], need[64], seen[64];
+  int32_t A0[3][64], B0[3][64], B1[3][64];
+  int32_t cum[2][64];  // candidates of case 0, of cases 0 and 1
+  uint32_t flags[64];  // bit 2cs: A of case cs is an in-list; bit 2cs + 1: B is
+};
+
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Edge of the batch holding candidate t (the last e with off[e] <= t).
+__device__ __forceinline__ int batch_edge(const PeelBatch &B, long long t) {
+  int e = 0;
+#pragma unroll
+  for (int s = 32; s > 0; s >>= 1)
+    if (B.off[e + s] <= t) e += s;
+  return e;
+}
+
+// Key of entry i of a sorted list: a stretch of col (stride 4 bytes) or of
+// in_edge (stride 8 bytes, key first).
+__device__ __forceinline__ int32_t list_key(const char *base, uint32_t sh, int32_t i) {
+  return *reinterpret_cast<const int32_t *>(base + ((uint64_t)(uint32_t)i << sh));
+}
+
+// find_many with a list per search: key[u] in col (bin[u] false) or in_edge
+// (bin[u] true) over [lo[u], hi[u]); out[u] = slot of the matching edge, or
+// -1.
+__device__ __forceinline__ void find_many_lists(const CsrView &c, const bool (&bin)[PEEL_U],
+                                                const int32_t (&lo)[PEEL_U],
+                                                const int32_t (&hi)[PEEL_U],
+                                                const int32_t (&key)[PEEL_U],
+                                                const bool (&act)[PEEL_U],
+                                                int32_t (&out)[PEEL_U]) {
+  const char *colp = reinterpret_cast<const char *>(c.col);
+  const char *inp = reinterpret_cast<const char *>(c.in_edge);
+  int32_t l[PEEL_U], n[PEEL_U];
+#pragma unroll
+  for (int u = 0; u < PEEL_U; ++u) { l[u] = lo[u]; n[u] = act[u] ? hi[u] - lo[u] : 0; }
+  for (;;) {
+    bool any = false;
+    int32_t v[PEEL_U];
+#pragma unroll
+    for (int u = 0; u < PEEL_U; ++u)
+      v[u] = n[u] > 0 ? list_key(bin[u] ? inp : colp, bin[u] ? 3 : 2, l[u] + (n[u] >> 1)) : 0;
+#pragma unroll
+    for (int u = 0; u < PEEL_U; ++u) {
+      if (n[u] > 0) {
+        const int32_t half = n[u] >> 1;
+        if (v[u] < key[u]) { l[u] += half + 1; n[u] -= half + 1; } else { n[u] = half; }
+        any |= n[u] > 0;
+      }
+    }
+    if (!any) break;
+  }
+#pragma unroll
+  for (int u = 0; u < PEEL_U; ++u) {
+    out[u] = -1;
+    if (act[u] && l[u] < hi[u]) {
+      if (bin[u]) {
+        const int2 ie = c.in_edge[l[u]];
+        if (ie.x == key[u]) out[u] = ie.y;
+      } else if (c.col[l[u]] == key[u]) {
+        out[u] = l[u];
+      }
+    }
+  }
+}
+
 // One round of level k over the frontier front[0, *front_count); the size is
 // read here, so rounds can be queued without the host knowing it.  `wpe`
 // waves share each frontier edge p = (a -> b).
@@ -191,12 +268,128 @@ __global__ __launch_bounds__(PBLK) void k_peel(CsrView c, const int32_t *__restr
                                                const uint8_t *__restrict__ state,
                                                int32_t *__restrict__ next,
                                                int32_t *__restrict__ next_count,
-                                               unsigned long long *__restrict__ work) {
+                                               unsigned long long *__restrict__ work,
+                                               int32_t lb_min) {
   const int lane = threadIdx.x & 63;
   int32_t n_cand = 0, n_search = 0, n_found = 0, n_ours = 0;  // per-lane work counters
   const int64_t gw = ((int64_t)blockIdx.x * PBLK + threadIdx.x) >> 6;
   const int64_t nw = ((int64_t)gridDim.x * PBLK) >> 6;
   const int32_t nfront = *front_count;
+  __shared__ PeelBatch batches[PBLK / 64];
+  if (nfront >= lb_min) {
+    PeelBatch &B = batches[threadIdx.x >> 6];
+    // edges per batch: 64, fewer when the frontier does not fill every wave
+    int32_t E = 64;
+    while (E > 1 && (int64_t)nfront < nw * E) E >>= 1;
+    const int64_t nbatch = ((int64_t)nfront + E - 1) / E;
+    for (int64_t bi = gw; bi < nbatch; bi += nw) {
+      // ---- the batch's edges, one per lane ----
+      const int64_t f = bi * E + lane;
+      int32_t p = -1, need = 0, tot = 0;
+      if (lane < E && f < nfront) {
+        p = front[f];
+        need = sup[p];
+      }
+      uint32_t fl = 0;
+      int32_t cum0 = 0, cum1 = 0;
+      if (need > 0) {
+        const PeelEdge pe = peel_edge(c, c.src[p], c.col[p]);
+#pragma unroll
+        for (int cs = 0; cs < 3; ++cs) {
+          const PeelCase pc = peel_case(pe, p, cs);
+          B.A0[cs][lane] = pc.A0;
+          B.B0[cs][lane] = pc.B0;
+          B.B1[cs][lane] = pc.B0 + pc.nB;
+          fl |= pc.flags << (2 * cs);
+          tot += pc.nA;
+          if (cs == 0) cum0 = tot;
+          if (cs == 1) cum1 = tot;
+        }
+      }
+      B.p[lane] = p;
+      B.need[lane] = need;
+      B.seen[lane] = 0;
+      B.cum[0][lane] = cum0;
+      B.cum[1][lane] = cum1;
+      B.flags[lane] = fl;
+      long long incl = tot;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const long long t = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += t;
+      }
+      B.off[lane] = incl - tot;
+      const long long T = __shfl(incl, 63, 64);
+      wave_lds_fence();
+      // ---- the concatenated candidates, 64 * PEEL_U per step ----
+      long long base = 0;
+      for (;;) {
+        // skip edges that have seen all their triangles
+        while (base < T) {
+          const int e0 = batch_edge(B, base);
+          if (B.seen[e0] < B.need[e0]) break;
+          base = e0 < 63 ? B.off[e0 + 1] : T;
+        }
+        if (base >= T) break;
+        int32_t eu[PEEL_U], qk[PEEL_U], key[PEEL_U], lo[PEEL_U], hi[PEEL_U], hit[PEEL_U];
+        bool bin[PEEL_U], act[PEEL_U];
+#pragma unroll
+        for (int u = 0; u < PEEL_U; ++u) {
+          const long long t = base + u * 64 + lane;
+          eu[u] = 0;
+          qk[u] = -1;
+          key[u] = 0;
+          lo[u] = 0;
+          hi[u] = 0;
+          bin[u] = false;
+          act[u] = false;
+          if (t < T) {
+            const int e = batch_edge(B, t);
+            eu[u] = e;
+            if (B.seen[e] < B.need[e]) {
+              const int32_t local = (int32_t)(t - B.off[e]);
+              const int32_t c0 = B.cum[0][e], c1 = B.cum[1][e];
+              const int cs = local < c0 ? 0 : (local < c1 ? 1 : 2);
+              const int32_t li = local - (cs == 0 ? 0 : (cs == 1 ? c0 : c1));
+              const uint32_t f2 = B.flags[e] >> (2 * cs);
+              const int32_t i = B.A0[cs][e] + li;
+              ++n_cand;
+              int32_t q, x;
+              if (f2 & 1u) {
+                const int2 ie = c.in_edge[i];
+                x = ie.x;
+                q = ie.y;
+              } else {
+                x = c.col[i];
+                q = i;
+              }
+              if (state[q] != EDGE_DEAD) {
+                qk[u] = q;
+                key[u] = x;
+                lo[u] = B.B0[cs][e];
+                hi[u] = B.B1[cs][e];
+                bin[u] = (f2 & 2u) != 0;
+                act[u] = true;
+                ++n_search;
+              }
+            }
+          }
+        }
+        find_many_lists(c, bin, lo, hi, key, act, hit);
+#pragma unroll
+        for (int u = 0; u < PEEL_U; ++u) {
+          const int32_t pe = act[u] ? B.p[eu[u]] : 0;
+          const int r = destroy(hit[u] >= 0, pe, qk[u], hit[u], thr, state, sup, next, next_count);
+          n_found += r & 1;
+          n_ours += r >> 1;
+          if (r & 1) atomicAdd(&B.seen[eu[u]], 1);
+        }
+        wave_lds_fence();
+        base += 64 * PEEL_U;
+      }
+      wave_lds_fence();
+    }
+  } else {
   // keep every wave busy: a small frontier shares each edge among wpe waves
   int32_t wpe = 1;
   while (wpe < 16 && (int64_t)nfront * wpe * 2 <= nw) wpe *= 2;
@@ -260,6 +453,7 @@ __global__ __launch_bounds__(PBLK) void k_peel(CsrView c, const int32_t *__restr
         }
       }
     }
+  }
   }
   if (work) {
     const int32_t a0 = wave_sum_i32(n_cand), a1 = wave_sum_i32(n_search);
@@ -577,6 +771,10 @@ gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStre
   int32_t kmax = 2;
   const int64_t peel_waves = 256 * 32;  // 32 waves per CU
   const unsigned peel_blocks = (unsigned)(peel_waves / (PBLK / 64));
+  // smallest frontier for the lane-balanced batches (GC_PEEL_LB_MIN; below
+  // it, or below one edge per wave, each edge gets whole waves)
+  int32_t lb_min = (int32_t)peel_waves;
+  if (const char *ev = getenv("GC_PEEL_LB_MIN")) lb_min = (int32_t)strtol(ev, nullptr, 10);
   int64_t *stats = g->peel_stats;
   for (int i = 0; i < 41; ++i) stats[i] = 0;
   // per-wave work counters (candidates, searches, triangles), summed at the end
@@ -660,7 +858,7 @@ gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStre
       for (int i = 0; i < batch; ++i, ++r) {
         int32_t *fr = buf[r & 1], *nx = buf[(r + 1) & 1];
         int32_t *cf = &ctl->cnt[r % 3], *cn = &ctl->cnt[(r + 1) % 3], *cz = &ctl->cnt[(r + 2) % 3];
-        k_peel<<<peel_blocks, PBLK, 0, s>>>(c, fr, cf, thr, sup, state, nx, cn, work);
+        k_peel<<<peel_blocks, PBLK, 0, s>>>(c, fr, cf, thr, sup, state, nx, cn, work, lb_min);
         GC_LAUNCH_CHECK();
         k_advance<<<4096, 256, 0, s>>>(fr, cf, nx, cn, cz, state, c.eid, tau, k - 1, ctl->st);
         GC_LAUNCH_CHECK();

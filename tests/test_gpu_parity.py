@@ -385,6 +385,28 @@ def test_decomposition_peel_equals_rounds(monkeypatch):
         g.free()
 
 
+@pytest.mark.parametrize("lb_min", ["1", "64", "2147483647"])
+def test_peel_lane_batches(monkeypatch, lb_min):
+    """The peel kernel's two schedules (lane-balanced batches of up to 64
+    frontier edges, or whole waves per edge) give the oracle's truss numbers:
+    GC_PEEL_LB_MIN = 1 takes batches in every round, 2^31 - 1 never."""
+    monkeypatch.setenv("GC_PEEL_LB_MIN", lb_min)
+    for label, (src, dst, n) in (("rmat13", gg.rmat(13, 16, seed=11)),
+                                 ("rgg11", gg.rgg(1 << 11, 24.0, seed=12)),
+                                 ("K45", gg.complete(45)), ("king", gg.king(30)),
+                                 ("tripartite", gg.complete_tripartite(5, 9, 20))):
+        say("case lane batches", lb_min, label)
+        g = gc.build_graph(src, dst, n)
+        u, v = oracle.normalise(src, dst, n)
+        tau_ref, kmax_ref = oracle.truss_decomposition(n, u, v, "peel")
+        tau, kmax = g.truss_decomposition()
+        assert kmax == kmax_ref, (label, kmax, kmax_ref)
+        assert np.array_equal(tau.cpu().numpy(), tau_ref), label
+        st = g.truss_stats()
+        assert st["triangles_destroyed"] == oracle.triangle_count(n, u, v), label
+        g.free()
+
+
 def test_ktruss_peel_equals_rounds(monkeypatch):
     """k-truss by peeling the levels 3 .. k and by Alg. 4's recount rounds give
     the same edge set and size, and both match the oracle's truss numbers."""
