@@ -619,6 +619,25 @@ __global__ void k_mask_live(const uint8_t *__restrict__ state, const int32_t *__
     if (state[i] != EDGE_DEAD) mask[eid[i]] = 1;
 }
 
+// Sort keys of a frontier: the higher endpoint of each edge.
+__global__ void k_front_keys(const int32_t *__restrict__ front, int32_t n,
+                             const int32_t *__restrict__ col, uint64_t *__restrict__ keys,
+                             uint32_t *__restrict__ vals) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t p = front[i];
+    keys[i] = (uint64_t)(uint32_t)col[p];
+    vals[i] = (uint32_t)p;
+  }
+}
+
+__global__ void k_front_store(const uint32_t *__restrict__ vals, int32_t n,
+                              int32_t *__restrict__ front) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    front[i] = (int32_t)vals[i];
+}
+
 __global__ void k_iota(int32_t *__restrict__ x, int32_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -775,6 +794,28 @@ gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStre
   // it, or below one edge per wave, each edge gets whole waves)
   int32_t lb_min = (int32_t)peel_waves;
   if (const char *ev = getenv("GC_PEEL_LB_MIN")) lb_min = (int32_t)strtol(ev, nullptr, 10);
+  // a level's first frontier is sorted by higher endpoint when it holds at
+  // least sort_min edges (GC_PEEL_SORT_MIN; 0: never), so that the waves of
+  // a batch search the same lists
+  int64_t sort_min = 100000;
+  if (const char *ev = getenv("GC_PEEL_SORT_MIN")) sort_min = strtoll(ev, nullptr, 10);
+  // frontier fr[0, nf) in order of higher endpoint (stable: ties keep their order)
+  auto sort_front = [&](int32_t *fr, int32_t nf) -> gc_status {
+    const size_t need = 2 * abytes<uint64_t>(nf) + 2 * abytes<uint32_t>(nf) +
+                        sort_scratch_bytes(nf) + 1024;
+    GC_TRY(g->ws.reserve(need));
+    uint64_t *ka = g->ws.take<uint64_t>(nf), *kb = g->ws.take<uint64_t>(nf);
+    uint32_t *va = g->ws.take<uint32_t>(nf), *vb = g->ws.take<uint32_t>(nf);
+    void *sscr = g->ws.take<char>(sort_scratch_bytes(nf));
+    k_front_keys<<<gsz(nf), 256, 0, s>>>(fr, nf, c.col, ka, va);
+    GC_LAUNCH_CHECK();
+    uint64_t *ks;
+    uint32_t *vs;
+    GC_TRY(radix_sort(ka, kb, va, vb, nf, g->bits, sscr, s, &ks, &vs));
+    k_front_store<<<gsz(nf), 256, 0, s>>>(vs, nf, fr);
+    GC_LAUNCH_CHECK();
+    return GC_OK;
+  };
   int64_t *stats = g->peel_stats;
   for (int i = 0; i < 41; ++i) stats[i] = 0;
   // per-wave work counters (candidates, searches, triangles), summed at the end
@@ -844,6 +885,13 @@ gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStre
     GC_TRY(exclusive_scan(flag, pos, L, g->ws.take<char>(scan_scratch_bytes((int64_t)L + 1)), s));
     k_collect_scatter<<<gsz(L), 256, 0, s>>>(list, L, flag, pos, state, buf[0]);
     GC_LAUNCH_CHECK();
+    int batch = 1;
+    if (sort_min > 0) {
+      int32_t nf = 0;
+      GC_HIP(hipMemcpyAsync(&nf, pos + L, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      GC_HIP(hipStreamSynchronize(s));
+      if (nf >= sort_min) GC_TRY(sort_front(buf[0], nf));
+    }
     k_level_start<<<1, 64, 0, s>>>(ctl->cnt, pos + L);
     GC_LAUNCH_CHECK();
     ++stats[0];
@@ -852,7 +900,7 @@ gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStre
     // ---- rounds of level k, queued in batches without waiting for their
     // sizes (a round whose frontier is empty does nothing); the host looks at
     // the counters between batches, to stop and to compact ----
-    int r = 0, batch = 1;
+    int r = 0;
     int32_t nfront = 0;
     for (;;) {
       for (int i = 0; i < batch; ++i, ++r) {

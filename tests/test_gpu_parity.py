@@ -385,17 +385,21 @@ def test_decomposition_peel_equals_rounds(monkeypatch):
         g.free()
 
 
-@pytest.mark.parametrize("lb_min", ["1", "64", "2147483647"])
-def test_peel_lane_batches(monkeypatch, lb_min):
+@pytest.mark.parametrize("lb_min,sort_min", [("1", "0"), ("64", "0"), ("2147483647", "0"),
+                                             ("1", "1"), ("2147483647", "1")])
+def test_peel_lane_batches(monkeypatch, lb_min, sort_min):
     """The peel kernel's two schedules (lane-balanced batches of up to 64
     frontier edges, or whole waves per edge) give the oracle's truss numbers:
-    GC_PEEL_LB_MIN = 1 takes batches in every round, 2^31 - 1 never."""
+    GC_PEEL_LB_MIN = 1 takes batches in every round, 2^31 - 1 never; with
+    GC_PEEL_SORT_MIN = 1 every level's first frontier is sorted by higher
+    endpoint."""
     monkeypatch.setenv("GC_PEEL_LB_MIN", lb_min)
+    monkeypatch.setenv("GC_PEEL_SORT_MIN", sort_min)
     for label, (src, dst, n) in (("rmat13", gg.rmat(13, 16, seed=11)),
                                  ("rgg11", gg.rgg(1 << 11, 24.0, seed=12)),
                                  ("K45", gg.complete(45)), ("king", gg.king(30)),
                                  ("tripartite", gg.complete_tripartite(5, 9, 20))):
-        say("case lane batches", lb_min, label)
+        say("case lane batches", lb_min, sort_min, label)
         g = gc.build_graph(src, dst, n)
         u, v = oracle.normalise(src, dst, n)
         tau_ref, kmax_ref = oracle.truss_decomposition(n, u, v, "peel")
