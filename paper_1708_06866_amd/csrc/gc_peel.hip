@@ -44,33 +44,65 @@ __device__ __forceinline__ int32_t find_col(const int32_t *__restrict__ col, int
   return (lo < end && col[lo] == key) ? lo : -1;
 }
 
-// Triangle {p, q1, q2} seen from frontier edge p (found == false: no
-// triangle).  Every active lane of the wave calls this together, so the
-// next-frontier appends are aggregated per wave.  Returns bit 0: the triangle
-// is still present (no edge of it died in an earlier round); bit 1: this call
-// destroyed it (p is its smallest frontier edge).
-__device__ __forceinline__ int destroy(bool found, int32_t p, int32_t q1, int32_t q2,
-                                       int32_t thr, const uint8_t *__restrict__ state,
-                                       int32_t *__restrict__ sup, int32_t *__restrict__ next,
-                                       int32_t *__restrict__ next_count) {
-  bool t1 = false, t2 = false, present = false, ours = false;
-  if (found) {
-    const uint8_t s1 = state[q1], s2 = state[q2];
-    present = s1 != EDGE_DEAD && s2 != EDGE_DEAD;
-    ours = present && !(s1 == EDGE_FRONT && q1 < p) && !(s2 == EDGE_FRONT && q2 < p);
-    if (ours) {
-      if (s1 == EDGE_ALIVE) t1 = atomicSub(&sup[q1], 1) == thr;
-      if (s2 == EDGE_ALIVE) t2 = atomicSub(&sup[q2], 1) == thr;
+constexpr int PEEL_U = 4;  // candidates per lane in flight
+
+// Triangles {p[u], q1[u], q2[u]} seen from frontier edges p[u] (found[u]
+// false: no triangle), the PEEL_U of a lane at once: their state loads, then
+// their support decrements, are issued together, and the next-frontier
+// appends of the whole wave take one atomic.  Every lane of the wave calls
+// this.  r[u] bit 0: the triangle is still present (no edge of it died in an
+// earlier round); bit 1: this call destroyed it (p[u] is its smallest frontier
+// edge), and each surviving edge of it lost one; an edge whose support drops
+// from thr to thr - 1 joins the next frontier (once).
+__device__ __forceinline__ void destroy_many(const bool (&found)[PEEL_U],
+                                             const int32_t (&p)[PEEL_U],
+                                             const int32_t (&q1)[PEEL_U],
+                                             const int32_t (&q2)[PEEL_U], int32_t thr,
+                                             const uint8_t *__restrict__ state,
+                                             int32_t *__restrict__ sup,
+                                             int32_t *__restrict__ next,
+                                             int32_t *__restrict__ next_count,
+                                             int (&r)[PEEL_U]) {
+  uint8_t s1[PEEL_U], s2[PEEL_U];
+#pragma unroll
+  for (int u = 0; u < PEEL_U; ++u) {
+    s1[u] = s2[u] = EDGE_DEAD;
+    if (found[u]) {
+      s1[u] = state[q1[u]];
+      s2[u] = state[q2[u]];
     }
   }
-  int32_t at = wave_append(t1, next_count);
-  if (t1) next[at] = q1;
-  at = wave_append(t2, next_count);
-  if (t2) next[at] = q2;
-  return (present ? 1 : 0) | (ours ? 2 : 0);
+  int32_t o1[PEEL_U], o2[PEEL_U];
+#pragma unroll
+  for (int u = 0; u < PEEL_U; ++u) {
+    const bool present = s1[u] != EDGE_DEAD && s2[u] != EDGE_DEAD;
+    const bool ours = present && !(s1[u] == EDGE_FRONT && q1[u] < p[u]) &&
+                      !(s2[u] == EDGE_FRONT && q2[u] < p[u]);
+    r[u] = (present ? 1 : 0) | (ours ? 2 : 0);
+    o1[u] = o2[u] = 0;
+    if (ours && s1[u] == EDGE_ALIVE) o1[u] = atomicSub(&sup[q1[u]], 1);
+    if (ours && s2[u] == EDGE_ALIVE) o2[u] = atomicSub(&sup[q2[u]], 1);
+  }
+  // an edge whose support drops from thr to thr - 1 joins the next frontier
+  int32_t cnt = 0;
+  bool t1[PEEL_U], t2[PEEL_U];
+#pragma unroll
+  for (int u = 0; u < PEEL_U; ++u) {
+    t1[u] = (r[u] & 2) && s1[u] == EDGE_ALIVE && o1[u] == thr;
+    t2[u] = (r[u] & 2) && s2[u] == EDGE_ALIVE && o2[u] == thr;
+    cnt += (t1[u] ? 1 : 0) + (t2[u] ? 1 : 0);
+  }
+  if (__ballot(cnt > 0) == 0) return;
+  const int32_t incl = wave_inclusive_scan(cnt);
+  int32_t at = 0;
+  if (__lane_id() == 63) at = atomicAdd(next_count, incl);
+  at = __shfl(at, 63, 64) + incl - cnt;
+#pragma unroll
+  for (int u = 0; u < PEEL_U; ++u) {
+    if (t1[u]) next[at++] = q1[u];
+    if (t2[u]) next[at++] = q2[u];
+  }
 }
-
-constexpr int PEEL_U = 4;  // candidates per lane in flight
 
 // Keys of the two list layouts: a row holds the neighbour (its slot is the
 // position), an in-list entry holds {neighbour, slot}.
@@ -376,13 +408,20 @@ __global__ __launch_bounds__(PBLK) void k_peel(CsrView c, const int32_t *__restr
           }
         }
         find_many_lists(c, bin, lo, hi, key, act, hit);
+        bool fnd[PEEL_U];
+        int32_t pe[PEEL_U];
+        int r[PEEL_U];
 #pragma unroll
         for (int u = 0; u < PEEL_U; ++u) {
-          const int32_t pe = act[u] ? B.p[eu[u]] : 0;
-          const int r = destroy(hit[u] >= 0, pe, qk[u], hit[u], thr, state, sup, next, next_count);
-          n_found += r & 1;
-          n_ours += r >> 1;
-          if (r & 1) atomicAdd(&B.seen[eu[u]], 1);
+          fnd[u] = hit[u] >= 0;
+          pe[u] = act[u] ? B.p[eu[u]] : 0;
+        }
+        destroy_many(fnd, pe, qk, hit, thr, state, sup, next, next_count, r);
+#pragma unroll
+        for (int u = 0; u < PEEL_U; ++u) {
+          n_found += r[u] & 1;
+          n_ours += r[u] >> 1;
+          if (r[u] & 1) atomicAdd(&B.seen[eu[u]], 1);
         }
         wave_lds_fence();
         base += 64 * PEEL_U;
@@ -443,13 +482,21 @@ __global__ __launch_bounds__(PBLK) void k_peel(CsrView c, const int32_t *__restr
         }
         if (B_in) find_many(c.in_edge, B0, B1, key, act, hit);
         else find_many(c.col, B0, B1, key, act, hit);
+        // q1, q2: the edges between x and the two ends of p (either order)
+        bool fnd[PEEL_U];
+        int32_t pe[PEEL_U];
+        int r[PEEL_U];
 #pragma unroll
         for (int u = 0; u < PEEL_U; ++u) {
-          // q1, q2: the edges between x and the two ends of p (either order)
-          const int r = destroy(hit[u] >= 0, p, qk[u], hit[u], thr, state, sup, next, next_count);
-          n_found += r & 1;
-          n_ours += r >> 1;
-          seen += __popcll(__ballot(r & 1));
+          fnd[u] = hit[u] >= 0;
+          pe[u] = p;
+        }
+        destroy_many(fnd, pe, qk, hit, thr, state, sup, next, next_count, r);
+#pragma unroll
+        for (int u = 0; u < PEEL_U; ++u) {
+          n_found += r[u] & 1;
+          n_ours += r[u] >> 1;
+          seen += __popcll(__ballot(r[u] & 1));
         }
       }
     }
