@@ -602,16 +602,6 @@ __global__ void k_compact_list(const int32_t *__restrict__ list, int32_t L,
   }
 }
 
-__global__ void k_collect_flags(const int32_t *__restrict__ list, int32_t L, int32_t thr,
-                                const uint8_t *__restrict__ state,
-                                const int32_t *__restrict__ sup, int32_t *__restrict__ flag) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < L;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t p = list[i];
-    flag[i] = state[p] == EDGE_ALIVE && sup[p] < thr ? 1 : 0;
-  }
-}
-
 // Minimum support and number of the live edges of `list` (which may also
 // hold dead ones): dmin = min, dalive += count.
 __global__ void k_level_min(const int32_t *__restrict__ list, int32_t L,
@@ -646,16 +636,66 @@ __global__ void k_level_min(const int32_t *__restrict__ list, int32_t L,
   }
 }
 
-__global__ void k_collect_scatter(const int32_t *__restrict__ list, int32_t L,
-                                  const int32_t *__restrict__ flag, const int32_t *__restrict__ pos,
-                                  uint8_t *__restrict__ state, int32_t *__restrict__ front) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < L;
-       i += (int64_t)gridDim.x * blockDim.x)
-    if (flag[i]) {
-      const int32_t p = list[i];
-      state[p] = EDGE_FRONT;
-      front[pos[i]] = p;
+// The level's first frontier, tile by tile: block b takes list entries
+// [b * CT_TILE, (b + 1) * CT_TILE), CT_PER consecutive ones per thread, marks
+// the live edges with support < thr as frontier, and writes them in list
+// order to tmp from the tile's own start; tile_cnt[b] = their number.
+constexpr int CT_PER = 16;
+constexpr int CT_TILE = 256 * CT_PER;
+
+__global__ __launch_bounds__(256) void k_collect_tiles(const int32_t *__restrict__ list, int32_t L,
+                                                       int32_t thr, uint8_t *__restrict__ state,
+                                                       const int32_t *__restrict__ sup,
+                                                       int32_t *__restrict__ tmp,
+                                                       int32_t *__restrict__ tile_cnt) {
+  __shared__ int32_t wtot[4];
+  const int64_t tile0 = (int64_t)blockIdx.x * CT_TILE;
+  const int64_t i0 = tile0 + (int64_t)threadIdx.x * CT_PER;
+  int32_t p[CT_PER];
+  if (i0 + CT_PER <= L) {
+    const int4 *l4 = reinterpret_cast<const int4 *>(list + i0);
+#pragma unroll
+    for (int q = 0; q < CT_PER / 4; ++q) {
+      const int4 v = l4[q];
+      p[4 * q] = v.x;
+      p[4 * q + 1] = v.y;
+      p[4 * q + 2] = v.z;
+      p[4 * q + 3] = v.w;
     }
+  } else {
+#pragma unroll
+    for (int k = 0; k < CT_PER; ++k) p[k] = i0 + k < L ? list[i0 + k] : -1;
+  }
+  uint32_t take = 0;  // bit k: entry k joins the frontier
+#pragma unroll
+  for (int k = 0; k < CT_PER; ++k)
+    if (p[k] >= 0 && state[p[k]] == EDGE_ALIVE && sup[p[k]] < thr) take |= 1u << k;
+  const int32_t cnt = __popc(take);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int32_t incl = wave_inclusive_scan(cnt);
+  if (lane == 63) wtot[w] = incl;
+  __syncthreads();
+  int32_t off = incl - cnt;
+  for (int i = 0; i < w; ++i) off += wtot[i];
+  if (threadIdx.x == 255) tile_cnt[blockIdx.x] = off + cnt;
+  int32_t *out = tmp + tile0 + off;
+#pragma unroll
+  for (int k = 0; k < CT_PER; ++k)
+    if ((take >> k) & 1u) {
+      state[p[k]] = EDGE_FRONT;
+      *out++ = p[k];
+    }
+}
+
+// Copy tile b's tile_cnt[b] entries of tmp to front[tile_pos[b] ...).
+__global__ void k_gather_tiles(const int32_t *__restrict__ tmp, const int32_t *__restrict__ tile_cnt,
+                               const int32_t *__restrict__ tile_pos, int32_t ntiles,
+                               int32_t *__restrict__ front) {
+  for (int64_t b = blockIdx.x; b < ntiles; b += gridDim.x) {
+    const int32_t cnt = tile_cnt[b], at = tile_pos[b];
+    const int32_t *src = tmp + b * CT_TILE;
+    for (int32_t i = threadIdx.x; i < cnt; i += blockDim.x) front[at + i] = src[i];
+  }
 }
 
 // mask[eid[p]] = 1 for every slot p whose edge is not dead
@@ -806,7 +846,9 @@ gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStre
     GC_TRY(dalloc(ps.front[i], sizeof(int32_t) * ((size_t)m + 1)));
   }
   GC_TRY(dalloc(ps.flag, sizeof(int32_t) * ((size_t)m + 1)));
-  GC_TRY(dalloc(ps.pos, sizeof(int32_t) * ((size_t)m + 2)));
+  // (m + 2 for the scans over slots; the level start also keeps two arrays of
+  // tile counts there, 2 * ceil(m / CT_TILE) + 2 <= m + 64 entries)
+  GC_TRY(dalloc(ps.pos, sizeof(int32_t) * ((size_t)m + 64)));
   GC_TRY(dalloc(ps.misc, 256));
   int32_t *misc = static_cast<int32_t *>(ps.misc.ptr);  // [0] count, [1] min
   int32_t *flag = static_cast<int32_t *>(ps.flag.ptr);
@@ -926,20 +968,27 @@ gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStre
     }
     // the level's first frontier: live edges with support < k - 2 (at least
     // the edge of minimum support)
-    k_collect_flags<<<gsz(L), 256, 0, s>>>(list, L, thr, state, sup, flag);
+    // (one pass over the list compacts each tile in place order into flag,
+    // a scan over the tile counts places the tiles, and the survivors are
+    // copied to the frontier: list order is kept)
+    const int32_t ntiles = (int32_t)(((int64_t)L + CT_TILE - 1) / CT_TILE);
+    int32_t *tile_cnt = pos, *tile_pos = pos + ntiles + 1;
+    k_collect_tiles<<<ntiles, 256, 0, s>>>(list, L, thr, state, sup, flag, tile_cnt);
     GC_LAUNCH_CHECK();
-    GC_TRY(g->ws.reserve(scan_scratch_bytes((int64_t)L + 1)));
-    GC_TRY(exclusive_scan(flag, pos, L, g->ws.take<char>(scan_scratch_bytes((int64_t)L + 1)), s));
-    k_collect_scatter<<<gsz(L), 256, 0, s>>>(list, L, flag, pos, state, buf[0]);
+    GC_TRY(g->ws.reserve(scan_scratch_bytes((int64_t)ntiles + 1)));
+    GC_TRY(exclusive_scan(tile_cnt, tile_pos, ntiles,
+                          g->ws.take<char>(scan_scratch_bytes((int64_t)ntiles + 1)), s));
+    k_gather_tiles<<<grid_for(ntiles, 1, 4096), 256, 0, s>>>(flag, tile_cnt, tile_pos, ntiles,
+                                                             buf[0]);
     GC_LAUNCH_CHECK();
     int batch = 1;
     if (sort_min > 0) {
       int32_t nf = 0;
-      GC_HIP(hipMemcpyAsync(&nf, pos + L, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      GC_HIP(hipMemcpyAsync(&nf, tile_pos + ntiles, sizeof(int32_t), hipMemcpyDeviceToHost, s));
       GC_HIP(hipStreamSynchronize(s));
       if (nf >= sort_min) GC_TRY(sort_front(buf[0], nf));
     }
-    k_level_start<<<1, 64, 0, s>>>(ctl->cnt, pos + L);
+    k_level_start<<<1, 64, 0, s>>>(ctl->cnt, tile_pos + ntiles);
     GC_LAUNCH_CHECK();
     ++stats[0];
     kmax = k - 1 > kmax ? k - 1 : kmax;
