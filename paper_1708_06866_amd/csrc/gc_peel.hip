@@ -564,9 +564,9 @@ __global__ void k_advance(const int32_t *__restrict__ front, const int32_t *__re
 
 // Start of the rounds of a level: the frontier count (from the collecting
 // scan) becomes counter 0, counters 1 and 2 start at zero.
-__global__ void k_level_start(int32_t *__restrict__ cnt, const int32_t *__restrict__ nfront) {
+__global__ void k_level_start(int32_t *__restrict__ cnt, int32_t nfront) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    cnt[0] = *nfront;
+    cnt[0] = nfront;
     cnt[1] = 0;
     cnt[2] = 0;
   }
@@ -576,7 +576,7 @@ __global__ void k_alive_flags(const int32_t *__restrict__ list, int32_t L,
                               const uint8_t *__restrict__ state, int32_t *__restrict__ flag) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < L;
        i += (int64_t)gridDim.x * blockDim.x)
-    flag[i] = state[list[i]] == EDGE_ALIVE ? 1 : 0;
+    flag[i] = state[list[i]] != EDGE_DEAD ? 1 : 0;
 }
 
 __global__ void k_compact_list(const int32_t *__restrict__ list, int32_t L,
@@ -602,40 +602,6 @@ __global__ void k_compact_list(const int32_t *__restrict__ list, int32_t L,
   }
 }
 
-// Minimum support and number of the live edges of `list` (which may also
-// hold dead ones): dmin = min, dalive += count.
-__global__ void k_level_min(const int32_t *__restrict__ list, int32_t L,
-                            const uint8_t *__restrict__ state, const int32_t *__restrict__ sup,
-                            int32_t *__restrict__ dmin, int32_t *__restrict__ dalive) {
-  int32_t v = 0x7fffffff, cnt = 0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < L;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t p = list[i];
-    if (state[p] == EDGE_ALIVE) {
-      v = min(v, sup[p]);
-      ++cnt;
-    }
-  }
-  for (int o = 32; o > 0; o >>= 1) {
-    v = min(v, __shfl_xor(v, o, 64));
-    cnt += __shfl_xor(cnt, o, 64);
-  }
-  __shared__ int32_t wmin[4], wcnt[4];
-  if ((threadIdx.x & 63) == 0) {
-    wmin[threadIdx.x >> 6] = v;
-    wcnt[threadIdx.x >> 6] = cnt;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    v = min(min(wmin[0], wmin[1]), min(wmin[2], wmin[3]));
-    cnt = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
-    if (cnt > 0) {
-      atomicMin(dmin, v);
-      atomicAdd(dalive, cnt);
-    }
-  }
-}
-
 // The level's first frontier, tile by tile: block b takes list entries
 // [b * CT_TILE, (b + 1) * CT_TILE), CT_PER consecutive ones per thread, marks
 // the live edges with support < thr as frontier, and writes them in list
@@ -643,12 +609,16 @@ __global__ void k_level_min(const int32_t *__restrict__ list, int32_t L,
 constexpr int CT_PER = 16;
 constexpr int CT_TILE = 256 * CT_PER;
 
+// With dmin != null it also takes the minimum support (atomicMin into *dmin)
+// and the number (atomicAdd into *dalive) of the live edges it reads.
 __global__ __launch_bounds__(256) void k_collect_tiles(const int32_t *__restrict__ list, int32_t L,
                                                        int32_t thr, uint8_t *__restrict__ state,
                                                        const int32_t *__restrict__ sup,
                                                        int32_t *__restrict__ tmp,
-                                                       int32_t *__restrict__ tile_cnt) {
-  __shared__ int32_t wtot[4];
+                                                       int32_t *__restrict__ tile_cnt,
+                                                       int32_t *__restrict__ dmin,
+                                                       int32_t *__restrict__ dalive) {
+  __shared__ int32_t wtot[4], wmin[4], wlive[4];
   const int64_t tile0 = (int64_t)blockIdx.x * CT_TILE;
   const int64_t i0 = tile0 + (int64_t)threadIdx.x * CT_PER;
   int32_t p[CT_PER];
@@ -667,14 +637,38 @@ __global__ __launch_bounds__(256) void k_collect_tiles(const int32_t *__restrict
     for (int k = 0; k < CT_PER; ++k) p[k] = i0 + k < L ? list[i0 + k] : -1;
   }
   uint32_t take = 0;  // bit k: entry k joins the frontier
+  int32_t vmin = 0x7fffffff, live = 0;
 #pragma unroll
   for (int k = 0; k < CT_PER; ++k)
-    if (p[k] >= 0 && state[p[k]] == EDGE_ALIVE && sup[p[k]] < thr) take |= 1u << k;
+    if (p[k] >= 0 && state[p[k]] == EDGE_ALIVE) {
+      const int32_t v = sup[p[k]];
+      vmin = min(vmin, v);
+      ++live;
+      if (v < thr) take |= 1u << k;
+    }
   const int32_t cnt = __popc(take);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int32_t incl = wave_inclusive_scan(cnt);
   if (lane == 63) wtot[w] = incl;
+  if (dmin) {
+    for (int o = 32; o > 0; o >>= 1) {
+      vmin = min(vmin, __shfl_xor(vmin, o, 64));
+      live += __shfl_xor(live, o, 64);
+    }
+    if (lane == 0) {
+      wmin[w] = vmin;
+      wlive[w] = live;
+    }
+  }
   __syncthreads();
+  if (dmin && threadIdx.x == 0) {
+    const int32_t bm = min(min(wmin[0], wmin[1]), min(wmin[2], wmin[3]));
+    const int32_t bl = wlive[0] + wlive[1] + wlive[2] + wlive[3];
+    if (bl > 0) {
+      atomicMin(dmin, bm);
+      atomicAdd(dalive, bl);
+    }
+  }
   int32_t off = incl - cnt;
   for (int i = 0; i < w; ++i) off += wtot[i];
   if (threadIdx.x == 255) tile_cnt[blockIdx.x] = off + cnt;
@@ -922,14 +916,36 @@ gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStre
   GC_HIP(hipMemsetAsync(ctl, 0, sizeof(Ctl), s));
   Ctl h_ctl;
   long long removed_base = 0;  // edges removed when L was last counted
+  int32_t thr_prev = 0;        // threshold of the last level (0 before the first)
 
   for (;;) {
     int32_t *sup = static_cast<int32_t *>(ps.sup[ps.cur].ptr);
     uint8_t *state = static_cast<uint8_t *>(ps.state[ps.cur].ptr);
-    // ---- level start: minimum support and number of the live edges ----
+    // ---- level start, one tiled pass over the live-edge list: minimum
+    // support and number of the live edges, and the edges of support
+    // thr_prev (every live edge has at least that support when a level ends,
+    // so if the minimum is thr_prev they are the next level's first frontier;
+    // otherwise none is taken).  Tiles are compacted in list order into
+    // flag, placed by a scan of their counts and copied to buf[0]. ----
+    int32_t nf = 0;
+    auto collect = [&](int32_t t, int32_t *dmin, int32_t *dalive) -> gc_status {
+      const int32_t ntiles = (int32_t)(((int64_t)L + CT_TILE - 1) / CT_TILE);
+      int32_t *tile_cnt = pos, *tile_pos = pos + ntiles + 1;
+      k_collect_tiles<<<ntiles, 256, 0, s>>>(list, L, t, state, sup, flag, tile_cnt, dmin, dalive);
+      GC_LAUNCH_CHECK();
+      GC_TRY(g->ws.reserve(scan_scratch_bytes((int64_t)ntiles + 1)));
+      GC_TRY(exclusive_scan(tile_cnt, tile_pos, ntiles,
+                            g->ws.take<char>(scan_scratch_bytes((int64_t)ntiles + 1)), s));
+      k_gather_tiles<<<grid_for(ntiles, 1, 4096), 256, 0, s>>>(flag, tile_cnt, tile_pos, ntiles,
+                                                               buf[0]);
+      GC_LAUNCH_CHECK();
+      GC_HIP(hipMemcpyAsync(&nf, tile_pos + ntiles, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      return GC_OK;
+    };
+    const int32_t thr_spec = thr_prev + 1;
     k_set_i32<<<1, 64, 0, s>>>(misc, 0x7fffffff, 0);
-    k_level_min<<<grid_for(L, 256, 2048), 256, 0, s>>>(list, L, state, sup, misc, misc + 1);
     GC_LAUNCH_CHECK();
+    GC_TRY(collect(thr_spec, misc, misc + 1));
     int32_t h[2];
     GC_HIP(hipMemcpyAsync(h, misc, sizeof(h), hipMemcpyDeviceToHost, s));
     GC_HIP(hipStreamSynchronize(s));
@@ -937,6 +953,10 @@ gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStre
     if (alive == 0) break;
     const int32_t k = h[0] + 3;   // first level that removes something
     const int32_t thr = k - 2;
+    if (thr != thr_spec && nf != 0) {
+      set_error("decomposition: live edge below the previous level's threshold");
+      return GC_EDEVICE;
+    }
     if (k > k_stop) {
       // every live edge survives the levels up to k_stop: the k_stop-truss
       if (mask) {
@@ -948,7 +968,7 @@ gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStre
     }
     if ((int64_t)alive * 2 < (int64_t)c.m) {
       // compact the CSR when at least half of it is dead
-      GC_TRY(compact_peel(g, ps, c, next_store, buf[0], 0, s));
+      GC_TRY(compact_peel(g, ps, c, next_store, buf[0], nf, s));
       sup = static_cast<int32_t *>(ps.sup[ps.cur].ptr);
       state = static_cast<uint8_t *>(ps.state[ps.cur].ptr);
       k_iota<<<gsz(c.m), 256, 0, s>>>(list, c.m);
@@ -966,29 +986,16 @@ gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStre
       { int32_t *t = list; list = list2; list2 = t; }
       L = alive;
     }
-    // the level's first frontier: live edges with support < k - 2 (at least
-    // the edge of minimum support)
-    // (one pass over the list compacts each tile in place order into flag,
-    // a scan over the tile counts places the tiles, and the survivors are
-    // copied to the frontier: list order is kept)
-    const int32_t ntiles = (int32_t)(((int64_t)L + CT_TILE - 1) / CT_TILE);
-    int32_t *tile_cnt = pos, *tile_pos = pos + ntiles + 1;
-    k_collect_tiles<<<ntiles, 256, 0, s>>>(list, L, thr, state, sup, flag, tile_cnt);
-    GC_LAUNCH_CHECK();
-    GC_TRY(g->ws.reserve(scan_scratch_bytes((int64_t)ntiles + 1)));
-    GC_TRY(exclusive_scan(tile_cnt, tile_pos, ntiles,
-                          g->ws.take<char>(scan_scratch_bytes((int64_t)ntiles + 1)), s));
-    k_gather_tiles<<<grid_for(ntiles, 1, 4096), 256, 0, s>>>(flag, tile_cnt, tile_pos, ntiles,
-                                                             buf[0]);
-    GC_LAUNCH_CHECK();
-    int batch = 1;
-    if (sort_min > 0) {
-      int32_t nf = 0;
-      GC_HIP(hipMemcpyAsync(&nf, tile_pos + ntiles, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    if (thr != thr_spec) {
+      // the minimum is above thr_prev: collect the live edges with support
+      // < k - 2 now
+      GC_TRY(collect(thr, nullptr, nullptr));
       GC_HIP(hipStreamSynchronize(s));
-      if (nf >= sort_min) GC_TRY(sort_front(buf[0], nf));
     }
-    k_level_start<<<1, 64, 0, s>>>(ctl->cnt, tile_pos + ntiles);
+    thr_prev = thr;
+    int batch = 1;
+    if (sort_min > 0 && nf >= sort_min) GC_TRY(sort_front(buf[0], nf));
+    k_level_start<<<1, 64, 0, s>>>(ctl->cnt, nf);
     GC_LAUNCH_CHECK();
     ++stats[0];
     kmax = k - 1 > kmax ? k - 1 : kmax;
