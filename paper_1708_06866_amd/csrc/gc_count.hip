@@ -438,7 +438,9 @@ template <class TB>
 static void launch_tc_lds(const CsrView &c, const int4 *ub, int64_t nu, const CountOut &o,
                           hipStream_t s) {
   constexpr int bytes = TB::SLOTS * 4;
-  constexpr int per_cu = bytes <= 8192 ? 16 : bytes <= 16384 ? 8 : bytes <= 32768 ? 4 : bytes <= 65536 ? 2 : 1;
+  // twice the blocks that fit at once: the grid-stride loop over units then
+  // ends with less imbalance
+  constexpr int per_cu = bytes <= 8192 ? 32 : bytes <= 16384 ? 16 : bytes <= 32768 ? 8 : bytes <= 65536 ? 4 : 2;
   k_tc_lds<TB><<<unit_grid(nu, per_cu), CBLK, 0, s>>>(c, ub, nu, o);
 }
 
@@ -690,18 +692,20 @@ __global__ __launch_bounds__(CBLK) void k_sup_lds(CsrView c, const int4 *__restr
                                                   int64_t nunits, int32_t *__restrict__ sup) {
   using TB = LinTable<LOGS>;
   constexpr int NS = TB::SLOTS;
+  // hits on the staged edge b -> c of table slot t within this unit: byte
+  // t % 4 of tcnt[t / 4] (at most one per in-edge of the unit, so < 2^8)
+  static_assert(UNIT_CHUNK < (1 << 8), "8-bit hit counters");
   __shared__ int4 mem[NS / 4];
-  __shared__ int32_t tslot[NS];  // oriented slot of the staged edge b -> c
-  __shared__ int32_t tcnt[NS];   // hits on that edge within this unit
+  __shared__ uint32_t tcnt[NS / 4];
   int32_t *tab = reinterpret_cast<int32_t *>(mem);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int64_t ui = blockIdx.x; ui < nunits; ui += gridDim.x) {
     const int4 U = units[ui];
     const int32_t rb = c.row_ptr[U.x], re = c.row_ptr[U.x + 1];
     TB::clear(tab);
-    for (int i = threadIdx.x; i < NS; i += CBLK) tcnt[i] = 0;
+    for (int i = threadIdx.x; i < NS / 4; i += CBLK) tcnt[i] = 0;
     __syncthreads();
-    for (int32_t i = rb + threadIdx.x; i < re; i += CBLK) tslot[TB::insert(tab, c.col[i])] = i;
+    for (int32_t i = rb + threadIdx.x; i < re; i += CBLK) TB::insert(tab, c.col[i]);
     __syncthreads();
     const int32_t j1 = U.z;
     Item it = first_item(c, U.y + wave, j1);
@@ -723,7 +727,7 @@ __global__ __launch_bounds__(CBLK) void k_sup_lds(CsrView c, const int4 *__restr
           const int32_t at = TB::find(tab, w[u], q[u]);
           if (at >= 0) {
             ++mine;
-            atomicAdd(&tcnt[at], 1);                            // edge b -> c
+            atomicAdd(&tcnt[at >> 2], 1u << ((at & 3) << 3));   // edge b -> c
             atomicAdd(&sup[it.o + 64 * u + lane], 1);           // edge a -> c
           }
         }
@@ -739,8 +743,13 @@ __global__ __launch_bounds__(CBLK) void k_sup_lds(CsrView c, const int4 *__restr
       }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < NS; i += CBLK)
-      if (tcnt[i]) atomicAdd(&sup[tslot[i]], tcnt[i]);
+    // each staged edge finds its table slot again and adds its hits
+    for (int32_t i = rb + threadIdx.x; i < re; i += CBLK) {
+      const int32_t w = c.col[i];
+      const int32_t at = TB::find(tab, w, TB::first(tab, w));
+      const uint32_t h = at >= 0 ? (tcnt[at >> 2] >> ((at & 3) << 3)) & 0xffu : 0u;
+      if (h) atomicAdd(&sup[i], (int32_t)h);
+    }
     __syncthreads();
   }
 }
@@ -830,8 +839,8 @@ gc_status slot_support(const CsrView &c, const UnitStore &u, int32_t *d_sup, hip
     switch (b) {
       case 0: k_sup_group<6, 16><<<unit_grid((nu + 15) / 16, 16), CBLK, 0, s>>>(c, ub, nu, d_sup); break;
       case 1: k_sup_lds<9><<<unit_grid(nu, 16), CBLK, 0, s>>>(c, ub, nu, d_sup); break;
-      case 2: k_sup_lds<12><<<unit_grid(nu, 4), CBLK, 0, s>>>(c, ub, nu, d_sup); break;
-      case 3: k_sup_lds<13><<<unit_grid(nu, 2), CBLK, 0, s>>>(c, ub, nu, d_sup); break;
+      case 2: k_sup_lds<12><<<unit_grid(nu, 8), CBLK, 0, s>>>(c, ub, nu, d_sup); break;
+      case 3: k_sup_lds<13><<<unit_grid(nu, 4), CBLK, 0, s>>>(c, ub, nu, d_sup); break;
       default: k_sup_search<<<unit_grid(nu, 8), CBLK, 0, s>>>(c, ub, nu, d_sup); break;
     }
     GC_LAUNCH_CHECK();
