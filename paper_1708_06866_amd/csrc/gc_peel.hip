@@ -871,7 +871,9 @@ gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStre
   int32_t L = m;
   int next_store = 0;
   int32_t kmax = 2;
-  const int64_t peel_waves = 256 * 32;  // 32 waves per CU
+  // 64 waves per CU, over twice what is resident: rounds hand out their work
+  // to waves statically, and small shares let the dispatcher even out the end
+  const int64_t peel_waves = 256 * 64;
   const unsigned peel_blocks = (unsigned)(peel_waves / (PBLK / 64));
   // smallest frontier for the lane-balanced batches (GC_PEEL_LB_MIN; below
   // it, or below one edge per wave, each edge gets whole waves)
