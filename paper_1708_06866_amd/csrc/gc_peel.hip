@@ -1013,7 +1013,7 @@ gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStre
         int32_t *cf = &ctl->cnt[r % 3], *cn = &ctl->cnt[(r + 1) % 3], *cz = &ctl->cnt[(r + 2) % 3];
         k_peel<<<peel_blocks, PBLK, 0, s>>>(c, fr, cf, thr, sup, state, nx, cn, work, lb_min);
         GC_LAUNCH_CHECK();
-        k_advance<<<4096, 256, 0, s>>>(fr, cf, nx, cn, cz, state, c.eid, tau, k - 1, ctl->st);
+        k_advance<<<1024, 256, 0, s>>>(fr, cf, nx, cn, cz, state, c.eid, tau, k - 1, ctl->st);
         GC_LAUNCH_CHECK();
       }
       GC_HIP(hipMemcpyAsync(&h_ctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
