@@ -916,7 +916,14 @@ gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStre
   GC_TRY(dalloc(ps.ctl, sizeof(Ctl)));
   Ctl *ctl = static_cast<Ctl *>(ps.ctl.ptr);
   GC_HIP(hipMemsetAsync(ctl, 0, sizeof(Ctl), s));
-  Ctl h_ctl;
+  // host copies of the counters, in pinned memory (fast device-to-host reads)
+  struct Pinned {
+    void *p = nullptr;
+    ~Pinned() { if (p) (void)hipHostFree(p); }
+  } pin;
+  GC_HIP(hipHostMalloc(&pin.p, 4096, hipHostMallocDefault));
+  Ctl &h_ctl = *static_cast<Ctl *>(pin.p);
+  int32_t *hq = reinterpret_cast<int32_t *>(static_cast<char *>(pin.p) + 2048);  // min, alive, nf
   long long removed_base = 0;  // edges removed when L was last counted
   int32_t thr_prev = 0;        // threshold of the last level (0 before the first)
 
@@ -941,19 +948,19 @@ gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStre
       k_gather_tiles<<<grid_for(ntiles, 1, 4096), 256, 0, s>>>(flag, tile_cnt, tile_pos, ntiles,
                                                                buf[0]);
       GC_LAUNCH_CHECK();
-      GC_HIP(hipMemcpyAsync(&nf, tile_pos + ntiles, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      GC_HIP(hipMemcpyAsync(&hq[2], tile_pos + ntiles, sizeof(int32_t), hipMemcpyDeviceToHost, s));
       return GC_OK;
     };
     const int32_t thr_spec = thr_prev + 1;
     k_set_i32<<<1, 64, 0, s>>>(misc, 0x7fffffff, 0);
     GC_LAUNCH_CHECK();
     GC_TRY(collect(thr_spec, misc, misc + 1));
-    int32_t h[2];
-    GC_HIP(hipMemcpyAsync(h, misc, sizeof(h), hipMemcpyDeviceToHost, s));
+    GC_HIP(hipMemcpyAsync(hq, misc, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     GC_HIP(hipStreamSynchronize(s));
-    const int32_t alive = h[1];
+    nf = hq[2];
+    const int32_t alive = hq[1];
     if (alive == 0) break;
-    const int32_t k = h[0] + 3;   // first level that removes something
+    const int32_t k = hq[0] + 3;   // first level that removes something
     const int32_t thr = k - 2;
     if (thr != thr_spec && nf != 0) {
       set_error("decomposition: live edge below the previous level's threshold");
@@ -995,6 +1002,7 @@ gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStre
       // < k - 2 now
       GC_TRY(collect(thr, nullptr, nullptr));
       GC_HIP(hipStreamSynchronize(s));
+      nf = hq[2];
     }
     thr_prev = thr;
     int batch = 1;
