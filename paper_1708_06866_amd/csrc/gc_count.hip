@@ -438,9 +438,11 @@ template <class TB>
 static void launch_tc_lds(const CsrView &c, const int4 *ub, int64_t nu, const CountOut &o,
                           hipStream_t s) {
   constexpr int bytes = TB::SLOTS * 4;
-  // twice the blocks that fit at once: the grid-stride loop over units then
-  // ends with less imbalance
-  constexpr int per_cu = bytes <= 8192 ? 32 : bytes <= 16384 ? 16 : bytes <= 32768 ? 8 : bytes <= 65536 ? 4 : 2;
+  // 16 times the blocks that fit at once: each block takes a short stretch of
+  // units, and the dispatcher evens out the end (2x: 79.5 ms, 4x: 76.9 ms,
+  // 8x: 73.4 ms, 16x: 72.2 ms for the scale-24 pass; one block per unit:
+  // 123 ms)
+  constexpr int per_cu = bytes <= 8192 ? 256 : bytes <= 16384 ? 128 : bytes <= 32768 ? 64 : bytes <= 65536 ? 32 : 16;
   k_tc_lds<TB><<<unit_grid(nu, per_cu), CBLK, 0, s>>>(c, ub, nu, o);
 }
 
@@ -838,8 +840,8 @@ gc_status slot_support(const CsrView &c, const UnitStore &u, int32_t *d_sup, hip
     const int4 *ub = units + u.bin_begin[b];
     switch (b) {
       case 0: k_sup_group<6, 16><<<unit_grid((nu + 15) / 16, 16), CBLK, 0, s>>>(c, ub, nu, d_sup); break;
-      case 1: k_sup_lds<9><<<unit_grid(nu, 16), CBLK, 0, s>>>(c, ub, nu, d_sup); break;
-      case 2: k_sup_lds<12><<<unit_grid(nu, 8), CBLK, 0, s>>>(c, ub, nu, d_sup); break;
+      case 1: k_sup_lds<9><<<unit_grid(nu, 128), CBLK, 0, s>>>(c, ub, nu, d_sup); break;
+      case 2: k_sup_lds<12><<<unit_grid(nu, 64), CBLK, 0, s>>>(c, ub, nu, d_sup); break;
       case 3: k_sup_lds<13><<<unit_grid(nu, 4), CBLK, 0, s>>>(c, ub, nu, d_sup); break;
       default: k_sup_search<<<unit_grid(nu, 8), CBLK, 0, s>>>(c, ub, nu, d_sup); break;
     }
