@@ -768,6 +768,27 @@ __global__ void k_rows2(const int32_t *__restrict__ row_ptr, const int32_t *__re
     nrow[r] = pos[row_ptr[r]];
 }
 
+// In-list entries whose edge survives a compaction keep their order (each
+// list stays sorted by source): iflag[j] = the edge of in-list entry j lives.
+__global__ void k_in_alive(const int2 *__restrict__ in_edge, int32_t m,
+                           const int32_t *__restrict__ flag, int32_t *__restrict__ iflag) {
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m;
+       j += (int64_t)gridDim.x * blockDim.x)
+    iflag[j] = flag[in_edge[j].y];
+}
+
+// Surviving in-list entries to their new places, with their slots renumbered.
+__global__ void k_in_compact(const int2 *__restrict__ in_edge, int32_t m,
+                             const int32_t *__restrict__ iflag, const int32_t *__restrict__ ipos,
+                             const int32_t *__restrict__ pos, int2 *__restrict__ nin) {
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m;
+       j += (int64_t)gridDim.x * blockDim.x)
+    if (iflag[j]) {
+      const int2 e = in_edge[j];
+      nin[ipos[j]] = make_int2(e.x, pos[e.y]);
+    }
+}
+
 static unsigned gsz(int64_t work) { return grid_for(work, 256, 65536); }
 
 struct PeelState {
@@ -815,8 +836,26 @@ static gc_status compact_peel(gc_graph *g, PeelState &ps, CsrView &c, int &next,
     k_remap<<<gsz(nfront), 256, 0, s>>>(front, nfront, pos);
     GC_LAUNCH_CHECK();
   }
-  GC_TRY(build_in_lists(n, kept, g->bits, w, g->ws, s));
+  // in-lists: drop the dead entries in place order and renumber their slots
+  // (no sort; the peel reads in_ptr and in_edge only, so the working copy
+  // carries no in_tail)
+  GC_TRY(dalloc(w.in_ptr, sizeof(int32_t) * ((size_t)n + 1)));
+  GC_TRY(dalloc(w.in_edge, sizeof(int2) * ((size_t)kept + 1)));
+  const size_t need = 2 * abytes<int32_t>((size_t)m + 1) + scan_scratch_bytes((int64_t)m + 1);
+  GC_TRY(g->ws.reserve(need));
+  int32_t *iflag = g->ws.take<int32_t>((size_t)m + 1), *ipos = g->ws.take<int32_t>((size_t)m + 1);
+  void *iscr = g->ws.take<char>(scan_scratch_bytes((int64_t)m + 1));
+  k_in_alive<<<gsz(m), 256, 0, s>>>(c.in_edge, m, flag, iflag);
+  GC_LAUNCH_CHECK();
+  GC_TRY(exclusive_scan(iflag, ipos, m, iscr, s));
+  k_in_compact<<<gsz(m), 256, 0, s>>>(c.in_edge, m, iflag, ipos, pos,
+                                      static_cast<int2 *>(w.in_edge.ptr));
+  GC_LAUNCH_CHECK();
+  k_rows2<<<gsz((int64_t)n + 1), 256, 0, s>>>(c.in_ptr, ipos, n,
+                                              static_cast<int32_t *>(w.in_ptr.ptr));
+  GC_LAUNCH_CHECK();
   c = w.view(n, kept);
+  c.in_tail = nullptr;
   next ^= 1;
   ps.cur = o;
   ++g->peel_stats[4];
