@@ -572,47 +572,18 @@ __global__ void k_level_start(int32_t *__restrict__ cnt, int32_t nfront) {
   }
 }
 
-__global__ void k_alive_flags(const int32_t *__restrict__ list, int32_t L,
-                              const uint8_t *__restrict__ state, int32_t *__restrict__ flag) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < L;
-       i += (int64_t)gridDim.x * blockDim.x)
-    flag[i] = state[list[i]] != EDGE_DEAD ? 1 : 0;
-}
-
-__global__ void k_compact_list(const int32_t *__restrict__ list, int32_t L,
-                               const int32_t *__restrict__ flag, const int32_t *__restrict__ pos,
-                               const int32_t *__restrict__ sup, int32_t *__restrict__ out,
-                               int32_t *__restrict__ dmin) {
-  int32_t v = 0x7fffffff;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < L;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    if (flag[i]) {
-      const int32_t p = list[i];
-      out[pos[i]] = p;
-      v = min(v, sup[p]);
-    }
-  }
-  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
-  __shared__ int32_t wmin[4];
-  if ((threadIdx.x & 63) == 0) wmin[threadIdx.x >> 6] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    v = min(min(wmin[0], wmin[1]), min(wmin[2], wmin[3]));
-    if (v != 0x7fffffff) atomicMin(dmin, v);
-  }
-}
-
-// The level's first frontier, tile by tile: block b takes list entries
-// [b * CT_TILE, (b + 1) * CT_TILE), CT_PER consecutive ones per thread, marks
-// the live edges with support < thr as frontier, and writes them in list
-// order to tmp from the tile's own start; tile_cnt[b] = their number.
+// The level's first frontier, tile by tile over the slots of the current
+// CSR: block b takes slots [b * CT_TILE, (b + 1) * CT_TILE), CT_PER
+// consecutive ones per thread (one 16-byte load of states, four of
+// supports), marks the live edges with support < thr as frontier, and writes
+// them in slot order to tmp from the tile's own start; tile_cnt[b] = their
+// number.  With dmin != null it also takes the minimum support (atomicMin
+// into *dmin) and the number (atomicAdd into *dalive) of the live edges.
 constexpr int CT_PER = 16;
 constexpr int CT_TILE = 256 * CT_PER;
 
-// With dmin != null it also takes the minimum support (atomicMin into *dmin)
-// and the number (atomicAdd into *dalive) of the live edges it reads.
-__global__ __launch_bounds__(256) void k_collect_tiles(const int32_t *__restrict__ list, int32_t L,
-                                                       int32_t thr, uint8_t *__restrict__ state,
+__global__ __launch_bounds__(256) void k_collect_tiles(int32_t m, int32_t thr,
+                                                       uint8_t *__restrict__ state,
                                                        const int32_t *__restrict__ sup,
                                                        int32_t *__restrict__ tmp,
                                                        int32_t *__restrict__ tile_cnt,
@@ -621,30 +592,37 @@ __global__ __launch_bounds__(256) void k_collect_tiles(const int32_t *__restrict
   __shared__ int32_t wtot[4], wmin[4], wlive[4];
   const int64_t tile0 = (int64_t)blockIdx.x * CT_TILE;
   const int64_t i0 = tile0 + (int64_t)threadIdx.x * CT_PER;
-  int32_t p[CT_PER];
-  if (i0 + CT_PER <= L) {
-    const int4 *l4 = reinterpret_cast<const int4 *>(list + i0);
+  uint8_t st[CT_PER];
+  int32_t sv[CT_PER];
+  if (i0 + CT_PER <= m) {
+    const uint4 b = *reinterpret_cast<const uint4 *>(state + i0);
+    const uint32_t w[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+    for (int k = 0; k < CT_PER; ++k) st[k] = (uint8_t)(w[k >> 2] >> ((k & 3) * 8));
+    const int4 *s4 = reinterpret_cast<const int4 *>(sup + i0);
 #pragma unroll
     for (int q = 0; q < CT_PER / 4; ++q) {
-      const int4 v = l4[q];
-      p[4 * q] = v.x;
-      p[4 * q + 1] = v.y;
-      p[4 * q + 2] = v.z;
-      p[4 * q + 3] = v.w;
+      const int4 v = s4[q];
+      sv[4 * q] = v.x;
+      sv[4 * q + 1] = v.y;
+      sv[4 * q + 2] = v.z;
+      sv[4 * q + 3] = v.w;
     }
   } else {
 #pragma unroll
-    for (int k = 0; k < CT_PER; ++k) p[k] = i0 + k < L ? list[i0 + k] : -1;
+    for (int k = 0; k < CT_PER; ++k) {
+      st[k] = i0 + k < m ? state[i0 + k] : (uint8_t)EDGE_DEAD;
+      sv[k] = i0 + k < m ? sup[i0 + k] : 0;
+    }
   }
-  uint32_t take = 0;  // bit k: entry k joins the frontier
+  uint32_t take = 0;  // bit k: slot i0 + k joins the frontier
   int32_t vmin = 0x7fffffff, live = 0;
 #pragma unroll
   for (int k = 0; k < CT_PER; ++k)
-    if (p[k] >= 0 && state[p[k]] == EDGE_ALIVE) {
-      const int32_t v = sup[p[k]];
-      vmin = min(vmin, v);
+    if (st[k] == EDGE_ALIVE) {
+      vmin = min(vmin, sv[k]);
       ++live;
-      if (v < thr) take |= 1u << k;
+      if (sv[k] < thr) take |= 1u << k;
     }
   const int32_t cnt = __popc(take);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -676,8 +654,8 @@ __global__ __launch_bounds__(256) void k_collect_tiles(const int32_t *__restrict
 #pragma unroll
   for (int k = 0; k < CT_PER; ++k)
     if ((take >> k) & 1u) {
-      state[p[k]] = EDGE_FRONT;
-      *out++ = p[k];
+      state[i0 + k] = EDGE_FRONT;
+      *out++ = (int32_t)(i0 + k);
     }
 }
 
@@ -717,12 +695,6 @@ __global__ void k_front_store(const uint32_t *__restrict__ vals, int32_t n,
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     front[i] = (int32_t)vals[i];
-}
-
-__global__ void k_iota(int32_t *__restrict__ x, int32_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    x[i] = (int32_t)i;
 }
 
 __global__ void k_set_i32(int32_t *__restrict__ x, int32_t a, int32_t b) {
@@ -792,11 +764,11 @@ __global__ void k_in_compact(const int2 *__restrict__ in_edge, int32_t m,
 static unsigned gsz(int64_t work) { return grid_for(work, 256, 65536); }
 
 struct PeelState {
-  DeviceBuffer sup[2], state[2], list[2], front[2], flag, pos, misc, work, ctl;
+  DeviceBuffer sup[2], state[2], front[2], flag, pos, misc, work, ctl;
   int cur = 0;  // which sup/state buffer is live
   ~PeelState() {
     for (int i = 0; i < 2; ++i) {
-      dfree(sup[i]); dfree(state[i]); dfree(list[i]); dfree(front[i]);
+      dfree(sup[i]); dfree(state[i]); dfree(front[i]);
     }
     dfree(flag); dfree(pos); dfree(misc); dfree(work); dfree(ctl);
   }
@@ -875,7 +847,6 @@ gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStre
   for (int i = 0; i < 2; ++i) {
     GC_TRY(dalloc(ps.sup[i], sizeof(int32_t) * ((size_t)m + 1)));
     GC_TRY(dalloc(ps.state[i], (size_t)m + 1));
-    GC_TRY(dalloc(ps.list[i], sizeof(int32_t) * ((size_t)m + 1)));
     GC_TRY(dalloc(ps.front[i], sizeof(int32_t) * ((size_t)m + 1)));
   }
   GC_TRY(dalloc(ps.flag, sizeof(int32_t) * ((size_t)m + 1)));
@@ -899,15 +870,10 @@ gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStre
     GC_TRY(slot_support(c, g->units_sup, sup, s));
     GC_HIP(hipMemsetAsync(ps.state[0].ptr, EDGE_ALIVE, (size_t)m, s));
   }
-  int32_t *list = static_cast<int32_t *>(ps.list[0].ptr);
-  int32_t *list2 = static_cast<int32_t *>(ps.list[1].ptr);
   // frontier buffers: a level collects into buf[0]; round r reads buf[r & 1]
   // and appends the next frontier to buf[(r + 1) & 1]
   int32_t *buf[2] = {static_cast<int32_t *>(ps.front[0].ptr),
                      static_cast<int32_t *>(ps.front[1].ptr)};
-  k_iota<<<gsz(m), 256, 0, s>>>(list, m);
-  GC_LAUNCH_CHECK();
-  int32_t L = m;
   int next_store = 0;
   int32_t kmax = 2;
   // 64 waves per CU, over twice what is resident: rounds hand out their work
@@ -963,23 +929,24 @@ gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStre
   GC_HIP(hipHostMalloc(&pin.p, 4096, hipHostMallocDefault));
   Ctl &h_ctl = *static_cast<Ctl *>(pin.p);
   int32_t *hq = reinterpret_cast<int32_t *>(static_cast<char *>(pin.p) + 2048);  // min, alive, nf
-  long long removed_base = 0;  // edges removed when L was last counted
+  long long removed_base = 0;  // edges removed when live was last counted
   int32_t thr_prev = 0;        // threshold of the last level (0 before the first)
 
   for (;;) {
     int32_t *sup = static_cast<int32_t *>(ps.sup[ps.cur].ptr);
     uint8_t *state = static_cast<uint8_t *>(ps.state[ps.cur].ptr);
-    // ---- level start, one tiled pass over the live-edge list: minimum
-    // support and number of the live edges, and the edges of support
+    // ---- level start, one tiled pass over the slots of the current CSR
+    // (at least three quarters of them live: it is compacted below that):
+    // minimum support and number of the live edges, and the edges of support
     // thr_prev (every live edge has at least that support when a level ends,
     // so if the minimum is thr_prev they are the next level's first frontier;
-    // otherwise none is taken).  Tiles are compacted in list order into
-    // flag, placed by a scan of their counts and copied to buf[0]. ----
+    // otherwise none is taken).  Tiles are compacted in slot order into flag,
+    // placed by a scan of their counts and copied to buf[0]. ----
     int32_t nf = 0;
     auto collect = [&](int32_t t, int32_t *dmin, int32_t *dalive) -> gc_status {
-      const int32_t ntiles = (int32_t)(((int64_t)L + CT_TILE - 1) / CT_TILE);
+      const int32_t ntiles = (int32_t)(((int64_t)c.m + CT_TILE - 1) / CT_TILE);
       int32_t *tile_cnt = pos, *tile_pos = pos + ntiles + 1;
-      k_collect_tiles<<<ntiles, 256, 0, s>>>(list, L, t, state, sup, flag, tile_cnt, dmin, dalive);
+      k_collect_tiles<<<ntiles, 256, 0, s>>>(c.m, t, state, sup, flag, tile_cnt, dmin, dalive);
       GC_LAUNCH_CHECK();
       GC_TRY(g->ws.reserve(scan_scratch_bytes((int64_t)ntiles + 1)));
       GC_TRY(exclusive_scan(tile_cnt, tile_pos, ntiles,
@@ -1021,20 +988,6 @@ gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStre
       GC_TRY(compact_peel(g, ps, c, next_store, buf[0], nf, s));
       sup = static_cast<int32_t *>(ps.sup[ps.cur].ptr);
       state = static_cast<uint8_t *>(ps.state[ps.cur].ptr);
-      k_iota<<<gsz(c.m), 256, 0, s>>>(list, c.m);
-      GC_LAUNCH_CHECK();
-      L = c.m;
-    } else if ((int64_t)alive * 2 < (int64_t)L) {
-      // drop the dead entries of the live-edge list when they are the majority
-      k_alive_flags<<<gsz(L), 256, 0, s>>>(list, L, state, flag);
-      GC_LAUNCH_CHECK();
-      GC_TRY(g->ws.reserve(scan_scratch_bytes((int64_t)L + 1)));
-      GC_TRY(exclusive_scan(flag, pos, L, g->ws.take<char>(scan_scratch_bytes((int64_t)L + 1)), s));
-      k_compact_list<<<grid_for(L, 256, 2048), 256, 0, s>>>(list, L, flag, pos, sup, list2,
-                                                            misc + 2);
-      GC_LAUNCH_CHECK();
-      { int32_t *t = list; list = list2; list2 = t; }
-      L = alive;
     }
     if (thr != thr_spec) {
       // the minimum is above thr_prev: collect the live edges with support
@@ -1073,9 +1026,6 @@ gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStre
         GC_TRY(compact_peel(g, ps, c, next_store, buf[r & 1], nfront, s));
         sup = static_cast<int32_t *>(ps.sup[ps.cur].ptr);
         state = static_cast<uint8_t *>(ps.state[ps.cur].ptr);
-        k_iota<<<gsz(c.m), 256, 0, s>>>(list, c.m);
-        GC_LAUNCH_CHECK();
-        L = c.m;
         live = c.m;
         removed_base = h_ctl.st[1];
       }
