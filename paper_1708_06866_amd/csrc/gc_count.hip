@@ -128,57 +128,80 @@ struct BucketTable {
   }
 };
 
-// ---- streaming the tails (software-pipelined) -----------------------------
-// A wave walks its in-edges j = j0, j0 + 4, ... < j1.  An "item" is one
-// 64 * TC_UNROLL element chunk of one in-edge's tail.  The loads of the next
-// item are issued before the current item is probed, so every wave keeps two
-// rounds of tail loads in flight while it works on the LDS table.
-struct Item {
-  int32_t j;   // in-edge (wave-uniform)
-  int2 t;      // its tail range
-  int32_t o;   // chunk start
-};
+// Make this wave's LDS stores visible to its other lanes (and its loads done
+// before later stores): within one wave a fence and a wave barrier suffice.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
-__device__ __forceinline__ Item first_item(const CsrView &c, int32_t j, int32_t j1) {
-  Item it;
-  it.t = make_int2(0, 0);
-  for (; j < j1; j += CWAVES) {
-    it.t = c.in_tail[j];
-    if (it.t.x < it.t.y) break;
+// ---- streaming the tails ---------------------------------------------------
+// A unit's staged table is probed with the tails of its in-edges.  Each wave
+// takes its in-edges of the unit (at most UNIT_CHUNK / CWAVES of them: j0,
+// j0 + CWAVES, ...), lays their tails end to end, and its lanes take
+// consecutive elements of that concatenation, 64 * TC_UNROLL per step, so
+// short tails do not leave lanes idle; the next step's loads are issued
+// before the current step is probed.  offs / xs: this wave's LDS arrays
+// (first element of each tail in the concatenation, and its position in
+// col).
+constexpr int TC_PACK = UNIT_CHUNK / CWAVES;
+static_assert(TC_PACK <= 64, "one in-edge per lane");
+
+__device__ __forceinline__ void pack_tails(const CsrView &c, int32_t j0, int32_t j1, int lane,
+                                           int32_t *offs, int32_t *xs, int32_t &total) {
+  int32_t x = 0, len = 0;
+  if (lane < TC_PACK) {
+    const int32_t j = j0 + lane * CWAVES;
+    if (j < j1) {
+      const int2 t = c.in_tail[j];
+      x = t.x;
+      len = t.y > t.x ? t.y - t.x : 0;
+    }
   }
-  it.j = j;
-  it.o = it.t.x;
-  return it;
+  const int32_t incl = wave_inclusive_scan(len);
+  if (lane < TC_PACK) {
+    offs[lane] = incl - len;
+    xs[lane] = x;
+  }
+  total = __shfl(incl, 63, 64);
 }
 
-__device__ __forceinline__ Item next_item(const CsrView &c, Item it, int32_t j1) {
-  it.o += 64 * TC_UNROLL;
-  if (it.o < it.t.y) return it;
-  Item n = first_item(c, it.j + CWAVES, j1);
-  return n;
-}
-
-__device__ __forceinline__ void load_item(const CsrView &c, const Item &it, int32_t j1, int lane,
-                                          int32_t (&w)[TC_UNROLL]) {
+// Tail element number t of the packing: its position in col (and in *kk,
+// the number of its in-edge in the packing).
+__device__ __forceinline__ int32_t packed_pos(const int32_t *offs, const int32_t *xs, int32_t t,
+                                              int *kk = nullptr) {
+  int k = 0;
 #pragma unroll
-  for (int u = 0; u < TC_UNROLL; ++u) {
-    const int32_t p = it.o + 64 * u + lane;
-    w[u] = (it.j < j1 && p < it.t.y) ? c.col[p] : -1;
-  }
+  for (int s = TC_PACK / 2; s > 0; s >>= 1)
+    if (offs[k + s] <= t) k += s;
+  if (kk) *kk = k;
+  return xs[k] + (t - offs[k]);
 }
 
 template <class TB>
-__device__ __forceinline__ int32_t probe_pipe(const int32_t *tab, const CsrView &c, int32_t j0,
-                                              int32_t j1, int lane) {
+__device__ __forceinline__ int32_t probe_packed(const int32_t *tab, const CsrView &c, int32_t j0,
+                                                int32_t j1, int lane, int32_t *offs,
+                                                int32_t *xs) {
+  int32_t total;
+  pack_tails(c, j0, j1, lane, offs, xs, total);
+  wave_lds_sync();
   int32_t hits = 0;
-  Item it = first_item(c, j0, j1);
-  if (it.j >= j1) return 0;
+  // (the tails are in distinct rows, so total <= m < 2^31; positions past it
+  // are formed in 64 bits)
   int32_t w[TC_UNROLL];
-  load_item(c, it, j1, lane, w);
-  for (;;) {
-    const Item nx = next_item(c, it, j1);
+#pragma unroll
+  for (int u = 0; u < TC_UNROLL; ++u) {
+    const int32_t t = 64 * u + lane;
+    w[u] = t < total ? c.col[packed_pos(offs, xs, t)] : -1;
+  }
+  for (int64_t base = 0; base < total; base += 64 * TC_UNROLL) {
     int32_t wn[TC_UNROLL];
-    load_item(c, nx, j1, lane, wn);   // in flight while we probe
+#pragma unroll
+    for (int u = 0; u < TC_UNROLL; ++u) {  // the next step, in flight while we probe
+      const int64_t t = base + 64 * TC_UNROLL + 64 * u + lane;
+      wn[u] = t < total ? c.col[packed_pos(offs, xs, (int32_t)t)] : -1;
+    }
     typename TB::Probe q[TC_UNROLL];
 #pragma unroll
     for (int u = 0; u < TC_UNROLL; ++u)
@@ -186,11 +209,10 @@ __device__ __forceinline__ int32_t probe_pipe(const int32_t *tab, const CsrView 
 #pragma unroll
     for (int u = 0; u < TC_UNROLL; ++u)
       if (w[u] >= 0 && TB::find(tab, w[u], q[u]) >= 0) ++hits;
-    if (nx.j >= j1) break;
-    it = nx;
 #pragma unroll
     for (int u = 0; u < TC_UNROLL; ++u) w[u] = wn[u];
   }
+  wave_lds_sync();  // offs / xs are rewritten for the next unit
   return hits;
 }
 
@@ -302,13 +324,15 @@ template <class TB>
 __global__ __launch_bounds__(CBLK) void k_tc_lds(CsrView c, const int4 *__restrict__ units,
                                                  int64_t nunits, CountOut out) {
   __shared__ int4 mem[TB::SLOTS / 4];
+  __shared__ int32_t poffs[CWAVES][TC_PACK], pxs[CWAVES][TC_PACK];
   int32_t *tab = reinterpret_cast<int32_t *>(mem);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   unsigned long long total = 0;  // wave-uniform
   for (int64_t ui = blockIdx.x; ui < nunits; ui += gridDim.x) {
     const int4 U = units[ui];
     stage_row<TB>(tab, c.col, c.row_ptr[U.x], c.row_ptr[U.x + 1]);
-    const int32_t sum = wave_sum_i32(probe_pipe<TB>(tab, c, U.y + wave, U.z, lane));
+    const int32_t sum =
+        wave_sum_i32(probe_packed<TB>(tab, c, U.y + wave, U.z, lane, poffs[wave], pxs[wave]));
     if (out.per_graph) {
       if (lane == 0 && sum) atomicAdd(&out.per_graph[out.graph_of_rank[U.x]], (unsigned long long)sum);
     } else {
@@ -317,14 +341,6 @@ __global__ __launch_bounds__(CBLK) void k_tc_lds(CsrView c, const int4 *__restri
     __syncthreads();
   }
   if (!out.per_graph && lane == 0 && total) atomicAdd(out.total, total);
-}
-
-// Make this wave's LDS stores visible to its other lanes (and its loads done
-// before later stores): within one wave a fence and a wave barrier suffice.
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Short out-lists (strategy 5): a group of GL lanes per unit with a table of
@@ -616,6 +632,7 @@ __global__ __launch_bounds__(CBLK) void k_tc_lds_multi(const GraphDesc *__restri
                                                        int32_t nh, int bin,
                                                        unsigned long long *__restrict__ out) {
   __shared__ int4 mem[TB::SLOTS / 4];
+  __shared__ int32_t poffs[CWAVES][TC_PACK], pxs[CWAVES][TC_PACK];
   int32_t *tab = reinterpret_cast<int32_t *>(mem);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t total = pre[nh];
@@ -624,7 +641,8 @@ __global__ __launch_bounds__(CBLK) void k_tc_lds_multi(const GraphDesc *__restri
     const CsrView c = d[g].c;
     const int4 U = d[g].units[d[g].bin_begin[bin] + (ui - pre[g])];
     stage_row<TB>(tab, c.col, c.row_ptr[U.x], c.row_ptr[U.x + 1]);
-    const int32_t sum = wave_sum_i32(probe_pipe<TB>(tab, c, U.y + wave, U.z, lane));
+    const int32_t sum =
+        wave_sum_i32(probe_packed<TB>(tab, c, U.y + wave, U.z, lane, poffs[wave], pxs[wave]));
     if (lane == 0 && sum) atomicAdd(&out[g], (unsigned long long)sum);
     __syncthreads();
   }
@@ -699,6 +717,7 @@ __global__ __launch_bounds__(CBLK) void k_sup_lds(CsrView c, const int4 *__restr
   static_assert(UNIT_CHUNK < (1 << 8), "8-bit hit counters");
   __shared__ int4 mem[NS / 4];
   __shared__ uint32_t tcnt[NS / 4];
+  __shared__ int32_t poffs[CWAVES][TC_PACK], pxs[CWAVES][TC_PACK], picnt[CWAVES][TC_PACK];
   int32_t *tab = reinterpret_cast<int32_t *>(mem);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int64_t ui = blockIdx.x; ui < nunits; ui += gridDim.x) {
@@ -709,40 +728,43 @@ __global__ __launch_bounds__(CBLK) void k_sup_lds(CsrView c, const int4 *__restr
     __syncthreads();
     for (int32_t i = rb + threadIdx.x; i < re; i += CBLK) TB::insert(tab, c.col[i]);
     __syncthreads();
-    const int32_t j1 = U.z;
-    Item it = first_item(c, U.y + wave, j1);
-    if (it.j < j1) {
-      int32_t w[TC_UNROLL];
-      load_item(c, it, j1, lane, w);
-      int32_t mine = 0;  // hits of the current in-edge (edge a -> b)
-      for (;;) {
-        const Item nx = next_item(c, it, j1);
-        int32_t wn[TC_UNROLL];
-        load_item(c, nx, j1, lane, wn);
-        typename TB::Probe q[TC_UNROLL];
+    // this wave's in-edges of the unit (U.y + wave, + CWAVES, ...), tails
+    // packed end to end as in the count; hits of in-edge k go to icnt[k]
+    int32_t *offs = poffs[wave], *xs = pxs[wave], *icnt = picnt[wave];
+    if (lane < TC_PACK) icnt[lane] = 0;
+    int32_t total;
+    pack_tails(c, U.y + wave, U.z, lane, offs, xs, total);
+    wave_lds_sync();
+    for (int64_t base = 0; base < total; base += 64 * TC_UNROLL) {
+      int32_t w[TC_UNROLL], pp[TC_UNROLL], kk[TC_UNROLL];
 #pragma unroll
-        for (int u = 0; u < TC_UNROLL; ++u)
-          if (w[u] >= 0) q[u] = TB::first(tab, w[u]);
-#pragma unroll
-        for (int u = 0; u < TC_UNROLL; ++u) {
-          if (w[u] < 0) continue;
-          const int32_t at = TB::find(tab, w[u], q[u]);
-          if (at >= 0) {
-            ++mine;
-            atomicAdd(&tcnt[at >> 2], 1u << ((at & 3) << 3));   // edge b -> c
-            atomicAdd(&sup[it.o + 64 * u + lane], 1);           // edge a -> c
-          }
+      for (int u = 0; u < TC_UNROLL; ++u) {
+        const int64_t t = base + 64 * u + lane;
+        w[u] = -1;
+        if (t < total) {
+          pp[u] = packed_pos(offs, xs, (int32_t)t, &kk[u]);
+          w[u] = c.col[pp[u]];
         }
-        if (nx.j != it.j) {  // the in-edge is complete
-          const int32_t tot = wave_sum_i32(mine);
-          if (lane == 0 && tot) atomicAdd(&sup[c.in_edge[it.j].y], tot);
-          mine = 0;
-        }
-        if (nx.j >= j1) break;
-        it = nx;
-#pragma unroll
-        for (int u = 0; u < TC_UNROLL; ++u) w[u] = wn[u];
       }
+      typename TB::Probe q[TC_UNROLL];
+#pragma unroll
+      for (int u = 0; u < TC_UNROLL; ++u)
+        if (w[u] >= 0) q[u] = TB::first(tab, w[u]);
+#pragma unroll
+      for (int u = 0; u < TC_UNROLL; ++u) {
+        if (w[u] < 0) continue;
+        const int32_t at = TB::find(tab, w[u], q[u]);
+        if (at >= 0) {
+          atomicAdd(&icnt[kk[u]], 1);                        // edge a -> b
+          atomicAdd(&tcnt[at >> 2], 1u << ((at & 3) << 3));  // edge b -> c
+          atomicAdd(&sup[pp[u]], 1);                         // edge a -> c
+        }
+      }
+    }
+    wave_lds_sync();
+    if (lane < TC_PACK) {
+      const int32_t j = U.y + wave + lane * CWAVES;
+      if (j < U.z && icnt[lane]) atomicAdd(&sup[c.in_edge[j].y], icnt[lane]);
     }
     __syncthreads();
     // each staged edge finds its table slot again and adds its hits
