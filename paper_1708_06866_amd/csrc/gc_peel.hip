@@ -10,10 +10,12 @@
 //
 // Round at level k (threshold t = k - 2; the frontier holds every live edge
 // whose support fell below t):
-//   * one wavefront per frontier edge p = (a -> b) enumerates the triangles
-//     {a, b, c} still present: c from the out-row of a (c > b: is c in the row
-//     of b? c < b: is b in the row of c?) and from the in-list of a (is b in
-//     the row of c?), each by binary search in a sorted row;
+//   * the triangles {a, b, x} of each frontier edge p = (a -> b) still present
+//     are enumerated in three cases by the rank of x, each intersecting a
+//     sorted list of a with one of b (the shorter iterated, each entry
+//     binary-searched in the other); large frontiers go in lane-balanced
+//     batches of up to 64 edges per wave, small ones give each edge whole
+//     waves (see k_peel);
 //   * a triangle is skipped if one of its edges died in an earlier round, or
 //     if another frontier edge of it has a smaller slot id (so each destroyed
 //     triangle is subtracted exactly once, whichever edges die together);
@@ -21,8 +23,10 @@
 //     drops from t to t - 1 joins the next frontier (once);
 //   * the frontier edges die with truss number k - 1.
 // A level ends when the frontier is empty.  The next level is min-support + 3
-// (every level in between removes nothing).  When a quarter of the
-// oriented CSR is dead it is compacted by a scan, carrying support and state.
+// (every level in between removes nothing); one tiled pass over the slots
+// finds the minimum and collects the level's first frontier.  When a quarter
+// of the oriented CSR is dead it is compacted by a scan, carrying support and
+// state, and its in-lists are filtered in place.
 //
 // Results equal the rounds of Alg. 4 (bulk removal per round, same frontier
 // sets); only the work per round differs.
@@ -33,16 +37,6 @@ namespace gc {
 enum : uint8_t { EDGE_ALIVE = 0, EDGE_FRONT = 1, EDGE_DEAD = 2 };
 
 constexpr int PBLK = 256;
-
-__device__ __forceinline__ int32_t find_col(const int32_t *__restrict__ col, int32_t lo,
-                                            int32_t hi, int32_t key) {
-  const int32_t end = hi;
-  while (lo < hi) {
-    const int32_t mid = lo + ((hi - lo) >> 1);
-    if (col[mid] < key) lo = mid + 1; else hi = mid;
-  }
-  return (lo < end && col[lo] == key) ? lo : -1;
-}
 
 constexpr int PEEL_U = 4;  // candidates per lane in flight
 
@@ -562,8 +556,8 @@ __global__ void k_advance(const int32_t *__restrict__ front, const int32_t *__re
   }
 }
 
-// Start of the rounds of a level: the frontier count (from the collecting
-// scan) becomes counter 0, counters 1 and 2 start at zero.
+// Start of the rounds of a level: the first frontier's size becomes counter
+// 0, counters 1 and 2 start at zero.
 __global__ void k_level_start(int32_t *__restrict__ cnt, int32_t nfront) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     cnt[0] = nfront;
