@@ -6,9 +6,11 @@
 // and is seen exactly once, at its middle vertex b: the oriented slot p holds
 // edge a -> b, the tail of row a after p holds every c > b with a -> c, and
 // the triangle exists iff c is also in N+(b).  A work unit is (b, a chunk of
-// b's in-list): the block stages N+(b) once in an LDS hash table, then its
-// waves stream the tails of the chunk's in-edges, one tail per wave, 64
-// consecutive elements per step (coalesced), 4 steps in flight per lane.
+// b's in-list): the block stages N+(b) once in an LDS hash table, then each
+// of its waves lays the tails of its in-edges of the chunk end to end and
+// streams that concatenation, 64 consecutive elements per load (coalesced
+// within a tail), 4 loads in flight per lane, so short tails do not leave
+// lanes idle.
 //
 // Two LDS table layouts: linear probing over single slots (LinTable), and
 // buckets of 4 slots in 16 bytes, filled in slot order, with linear probing
@@ -17,16 +19,17 @@
 // is seen.  The reads of the 4 in-flight elements are issued together.
 //
 // Degree bins pick the table size: d+(b) <= 32, 256, 2048 and 8192 (count) /
-// 4096 (support).  Per bin the count chooses one of five strategies (see
+// 4096 (support).  Per bin the count chooses one of six strategies (see
 // count_strategy_valid): either layout with at most half or a quarter of the
-// slots used, or binary search of N+(b) in HBM (the only one for the last,
-// unbounded bin).  The autotuner times them per bin on the graph at hand.
+// slots used, binary search of N+(b) in HBM (the only one for the last,
+// unbounded bin), or for bins 0 and 1 a lane group per unit with its own
+// table.  The autotuner times them per bin on the graph at hand.
 //
 // Support: a hit (a, b, c) adds one to each of its three edges.  a -> b (the
-// in-edge) is summed over the wave and added once per in-edge; b -> c (the
-// staged edge) is counted in an LDS counter beside the table slot and
-// flushed once per unit; a -> c (the streamed element) takes one global
-// atomic.
+// in-edge) is counted in an LDS counter per packed in-edge and added once per
+// unit; b -> c (the staged edge) in an 8-bit LDS counter per table slot,
+// added once per unit after each staged edge finds its slot again; a -> c
+// (the streamed element) takes one global atomic.
 #include <stdio.h>
 #include <stdlib.h>
 
