@@ -158,7 +158,17 @@ gc_status gc_graph_set_strategy(gc_graph *g, const int32_t *h_strategy);
 /* Truss decomposition (Sec. III-B, last paragraph): d_truss[e] = the largest
  * k such that canonical edge e belongs to the k-truss (>= 2), and *h_kmax the
  * largest k with a non-empty k-truss (0 for an empty graph, 2 if there are
- * edges but no triangle).  Either output may be NULL.  Synchronises `stream`. */
+ * edges but no triangle).  Either output may be NULL.  Synchronises `stream`.
+ * Computed by peeling: support is counted once, then each level k removes in
+ * rounds every edge whose support falls below k-2, decrementing the support
+ * of the survivors once per destroyed triangle.  GC_TRUSS_METHOD=rounds
+ * recounts support per round instead (Alg. 4's recompute form).  Two
+ * environment variables tune the peeling without changing any result:
+ * GC_PEEL_LB_MIN (smallest frontier handled in lane-balanced batches of up
+ * to 64 edges per wave; default one edge per wave of the grid) and
+ * GC_PEEL_SORT_MIN (smallest first frontier of a level that is sorted by
+ * higher endpoint; default 100000, 0 = never).  Device memory: about 27
+ * bytes per edge of working state besides the graph, released on return. */
 gc_status gc_truss_decomposition(gc_graph *g, int32_t *d_truss, int64_t cap,
                                  gc_stream stream, int32_t *h_kmax);
 
