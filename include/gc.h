@@ -167,8 +167,10 @@ gc_status gc_graph_set_strategy(gc_graph *g, const int32_t *h_strategy);
  * GC_PEEL_LB_MIN (smallest frontier handled in lane-balanced batches of up
  * to 64 edges per wave; default one edge per wave of the grid) and
  * GC_PEEL_SORT_MIN (smallest first frontier of a level that is sorted by
- * higher endpoint; default 100000, 0 = never).  Device memory: about 27
- * bytes per edge of working state besides the graph, released on return. */
+ * higher endpoint; default 100000, 0 = never).  Device memory: about 26
+ * bytes per edge of working state, released on return, and the compacted
+ * copies of the CSR (two at most, at most 20 bytes per edge each), which the
+ * handle keeps for reuse until gc_graph_free. */
 gc_status gc_truss_decomposition(gc_graph *g, int32_t *d_truss, int64_t cap,
                                  gc_stream stream, int32_t *h_kmax);
 
