@@ -174,9 +174,10 @@ gc_status gc_graph_set_strategy(gc_graph *g, const int32_t *h_strategy);
 gc_status gc_truss_decomposition(gc_graph *g, int32_t *d_truss, int64_t cap,
                                  gc_stream stream, int32_t *h_kmax);
 
-/* Counters of the last gc_truss_decomposition on this handle (first `cap`
- * of 41, host): [0] levels that removed edges, [1] rounds, [2] edges removed
- * over all rounds (= m), [3] largest round, [4] compactions of the edge list,
+/* Counters of the last peeling on this handle (gc_truss_decomposition, or
+ * gc_ktruss with k > 2 unless GC_TRUSS_METHOD=rounds; first `cap` of 41,
+ * host): [0] levels that removed edges, [1] rounds, [2] edges removed over
+ * all rounds (= m for a decomposition), [3] largest round, [4] compactions,
  * [5 + i] rounds whose removal count r has floor(log2 r) = i, [37]
  * candidate third vertices examined, [38] of them searched (edge alive),
  * [39] triangles found still present, [40] triangles destroyed (each
