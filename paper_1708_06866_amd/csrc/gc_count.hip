@@ -347,9 +347,9 @@ __global__ __launch_bounds__(CBLK) void k_tc_lds(CsrView c, const int4 *__restri
 }
 
 // Short out-lists (strategy 5): a group of GL lanes per unit with a table of
-// its own in LDS, so there are no block barriers; lane l of the group takes
-// the unit's in-edges first + l, first + l + GL, ... and walks each tail on
-// its own.  Suits graphs whose units are many and small (tails of a few
+// its own in LDS, so there are no block barriers; the group lays the tails
+// of GL in-edges at a time end to end and its lanes take consecutive
+// elements.  Suits graphs whose units are many and small (tails of a few
 // elements, as in sparse uniform graphs), where a block per unit would mostly
 // wait at barriers.  The lanes of a group always hold the same unit, so they
 // stay converged; groups of one wave may be at different units (each only
@@ -373,19 +373,40 @@ __global__ __launch_bounds__(CBLK) void k_tc_group(CsrView c, const int4 *__rest
     for (int32_t i = rb + gl; i < re; i += GL) TB::insert(tab, c.col[i]);
     wave_lds_sync();
     int32_t mine = 0;
-    for (int32_t j = U.y + gl; j < U.z; j += GL) {
-      const int2 t = c.in_tail[j];
-      int32_t p = t.x;
-      for (; p + 4 <= t.y; p += 4) {
+    // GL in-edges at a time: their tails laid end to end (offsets by a scan
+    // over the group), the group's lanes take consecutive elements, 4 in
+    // flight per lane; the tail of an element is found by a search over the
+    // GL offsets held in the lanes
+    for (int32_t j0 = U.y; j0 < U.z; j0 += GL) {
+      const int32_t j = j0 + gl;
+      int32_t x = 0, len = 0;
+      if (j < U.z) {
+        const int2 t = c.in_tail[j];
+        x = t.x;
+        len = t.y > t.x ? t.y - t.x : 0;
+      }
+      int32_t incl = len;
+#pragma unroll
+      for (int o = 1; o < GL; o <<= 1) {
+        const int32_t v = __shfl_up(incl, o, GL);
+        if (gl >= o) incl += v;
+      }
+      const int32_t total = __shfl(incl, GL - 1, GL), excl = incl - len;
+      for (int32_t t0 = 0; t0 < total; t0 += 4 * GL) {
         int32_t w[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) w[u] = c.col[p + u];
+        for (int u = 0; u < 4; ++u) {
+          const int32_t t = t0 + u * GL + gl;
+          int k = 0;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) mine += TB::find(tab, w[u], TB::first(tab, w[u])) >= 0;
-      }
-      for (; p < t.y; ++p) {
-        const int32_t w = c.col[p];
-        mine += TB::find(tab, w, TB::first(tab, w)) >= 0;
+          for (int s2 = GL / 2; s2 > 0; s2 >>= 1)
+            if (__shfl(excl, k + s2, GL) <= t) k += s2;
+          const int32_t xk = __shfl(x, k, GL), ek = __shfl(excl, k, GL);
+          w[u] = t < total ? c.col[xk + (t - ek)] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (w[u] >= 0) mine += TB::find(tab, w[u], TB::first(tab, w[u])) >= 0;
       }
     }
     if (out.per_graph) {
@@ -794,8 +815,9 @@ __global__ __launch_bounds__(CBLK) void k_sup_group(CsrView c, const int4 *__res
   __shared__ int32_t tabs[GPB][NS];
   __shared__ int32_t slots[GPB][NS];  // oriented slot of the staged edge b -> c
   __shared__ int32_t cnts[GPB][NS];   // hits on that edge within this unit
+  __shared__ int32_t icnts[GPB][GL];  // hits of the group's current in-edges
   const int gl = threadIdx.x % GL, grp = threadIdx.x / GL;
-  int32_t *tab = tabs[grp], *tslot = slots[grp], *tcnt = cnts[grp];
+  int32_t *tab = tabs[grp], *tslot = slots[grp], *tcnt = cnts[grp], *icnt = icnts[grp];
   const int64_t gid = ((int64_t)blockIdx.x * CBLK + threadIdx.x) / GL;
   const int64_t ng = (int64_t)gridDim.x * GPB;
   for (int64_t ui = gid; ui < nunits; ui += ng) {
@@ -808,19 +830,53 @@ __global__ __launch_bounds__(CBLK) void k_sup_group(CsrView c, const int4 *__res
     wave_lds_sync();
     for (int32_t i = rb + gl; i < re; i += GL) tslot[TB::insert(tab, c.col[i])] = i;
     wave_lds_sync();
-    for (int32_t j = U.y + gl; j < U.z; j += GL) {
-      const int2 t = c.in_tail[j];
-      int32_t mine = 0;  // hits of in-edge j (edge a -> b)
-      for (int32_t p = t.x; p < t.y; ++p) {
-        const int32_t w = c.col[p];
-        const int32_t at = TB::find(tab, w, TB::first(tab, w));
-        if (at >= 0) {
-          ++mine;
-          atomicAdd(&tcnt[at], 1);  // edge b -> c
-          atomicAdd(&sup[p], 1);    // edge a -> c
+    // GL in-edges at a time, tails packed as in k_tc_group; hits of in-edge
+    // k of the chunk go to icnt[k]
+    for (int32_t j0 = U.y; j0 < U.z; j0 += GL) {
+      const int32_t j = j0 + gl;
+      int32_t x = 0, len = 0;
+      if (j < U.z) {
+        const int2 t = c.in_tail[j];
+        x = t.x;
+        len = t.y > t.x ? t.y - t.x : 0;
+      }
+      icnt[gl] = 0;
+      int32_t incl = len;
+#pragma unroll
+      for (int o = 1; o < GL; o <<= 1) {
+        const int32_t v = __shfl_up(incl, o, GL);
+        if (gl >= o) incl += v;
+      }
+      const int32_t total = __shfl(incl, GL - 1, GL), excl = incl - len;
+      wave_lds_sync();
+      for (int32_t t0 = 0; t0 < total; t0 += 4 * GL) {
+        int32_t w[4], pp[4], kk[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int32_t t = t0 + u * GL + gl;
+          int k = 0;
+#pragma unroll
+          for (int s2 = GL / 2; s2 > 0; s2 >>= 1)
+            if (__shfl(excl, k + s2, GL) <= t) k += s2;
+          const int32_t xk = __shfl(x, k, GL), ek = __shfl(excl, k, GL);
+          kk[u] = k;
+          pp[u] = xk + (t - ek);
+          w[u] = t < total ? c.col[pp[u]] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (w[u] < 0) continue;
+          const int32_t at = TB::find(tab, w[u], TB::first(tab, w[u]));
+          if (at >= 0) {
+            atomicAdd(&icnt[kk[u]], 1);  // edge a -> b
+            atomicAdd(&tcnt[at], 1);     // edge b -> c
+            atomicAdd(&sup[pp[u]], 1);   // edge a -> c
+          }
         }
       }
-      if (mine) atomicAdd(&sup[c.in_edge[j].y], mine);
+      wave_lds_sync();
+      if (j < U.z && icnt[gl]) atomicAdd(&sup[c.in_edge[j].y], icnt[gl]);
+      wave_lds_sync();  // icnt is cleared for the next chunk
     }
     wave_lds_sync();
     for (int i = gl; i < NS; i += GL)
