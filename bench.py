@@ -464,8 +464,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on exactly one GPU: multi-GPU execution is not part of this "
-              "build (the design for sharding is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: multi-GPU execution (sharding work units "
+              "by byte weight, exchanging support deltas) is designed but not implemented",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
