@@ -80,3 +80,40 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(gc, "_lib", None)
     with pytest.raises(ImportError):
         gc.lib()
+
+
+def test_null_handles_rejected_on_the_host(lib):
+    """Every entry point that takes a handle answers GC_EINVAL for a NULL one
+    before any device work; the free calls accept NULL."""
+    P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    calls = (
+        ("gc_graph_info", [P, P, P, P], [None, None, None, None]),
+        ("gc_graph_edges", [P, P, P, I64, P], [None, None, None, 0, None]),
+        ("gc_graph_oriented", [P, P, P, P, P, I64, I64, P], [None] * 5 + [0, 0, None]),
+        ("gc_edge_support", [P, P, I64, P], [None, None, 0, None]),
+        ("gc_graph_autotune", [P, P, P, P], [None, None, None, None]),
+        ("gc_graph_set_strategy", [P, P], [None, None]),
+        ("gc_graph_truss_stats", [P, P, I32], [None, None, 0]),
+        ("gc_batch_info", [P, P, P, P], [None, None, None, None]),
+        ("gc_batch_edge_offsets", [P, P], [None, None]),
+        ("gc_batch_triangle_count", [P, P, P], [None, None, None]),
+        ("gc_batch_edge_support", [P, P, I64, P], [None, None, 0, None]),
+        ("gc_batch_ktruss", [P, I32, P, I64, P, P], [None, 3, None, 0, None, None]),
+        ("gc_batch_set_strategy", [P, P], [None, None]),
+        ("gc_server_set_mode", [P, I32], [None, 0]),
+        ("gc_server_submit", [P, P, P], [None, None, None]),
+        ("gc_server_poll", [P, I64, P], [None, 0, None]),
+        ("gc_server_stats", [P, P], [None, None]),
+        ("gc_server_create", [I64, P], [0, None]),
+        ("gc_read_edges", [P, I32, P, P, I64, P, P], [None, 0, None, None, 0, None, None]),
+    )
+    for name, argtypes, args in calls:
+        f = getattr(lib, name)
+        f.argtypes = argtypes
+        f.restype = ctypes.c_int32
+        assert f(*args) == -1, name
+    for name in ("gc_graph_free", "gc_batch_free", "gc_server_destroy"):
+        f = getattr(lib, name)
+        f.argtypes = [P]
+        f.restype = None
+        f(None)
