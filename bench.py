@@ -617,6 +617,12 @@ def main():
         "phases_ms": {"build": build_ms, "triangle_count": tc_ms, "decomposition": dec_ms},
         "autotune": tuned,
         "decomposition_stats": record_stats or None,
+        # the decomposition's dominant kernel (k_peel) is bound by the L1
+        # misses a CU keeps in flight, not by HBM bandwidth: its rate is
+        # given in candidate third vertices examined per second of the
+        # decomposition phase
+        "peel_candidates_per_s": (record_stats["candidates"] / (dec_ms / 1000.0)
+                                  if record_stats and dec_ms > 0 else None),
         "tc_edges_per_s": m / (tc_ms / 1000.0),
         # Sec. IV metrics beside the rate: energy of the timed steps from the
         # GPU's energy counter, rate per watt, and device memory
