@@ -34,7 +34,8 @@
  *   before returning.  Device inputs must stay valid until the stream has
  *   passed the call.
  *
- *   Errors: calls never abort.  They return GC_OK (0) or a negative status;
+ *   Errors: calls never abort and no C++ exception leaves them.  They return
+ *   GC_OK (0) or a negative status;
  *   gc_last_error() gives a thread-local description of the last failure.  On
  *   failure, outputs are unspecified and the handle stays valid.
  *
@@ -61,7 +62,8 @@ typedef void *gc_stream; /* a hipStream_t */
 #define GC_EINVAL (-1)     /* null pointer, negative size, bad flag, k < 2 */
 #define GC_ERANGE (-2)     /* a vertex id outside [0, n_vertices) */
 #define GC_ECAPACITY (-3)  /* output buffer shorter than required */
-#define GC_ENOMEM (-4)     /* device allocation failed */
+#define GC_ENOMEM (-4)     /* device or host allocation failed, or a host
+                              thread could not start */
 #define GC_EDEVICE (-5)    /* a HIP runtime error */
 #define GC_EOVERFLOW (-6)  /* a size beyond the limits above */
 

@@ -11,6 +11,14 @@ static thread_local std::string t_last_error;
 void set_error(const std::string &msg) { t_last_error = msg; }
 void clear_error() { t_last_error.clear(); }
 
+void note_host_failure(const char *where, const char *what) noexcept {
+  try {
+    t_last_error = std::string(where) + ": host allocation or thread start failed: " + what;
+  } catch (...) {
+    t_last_error.clear();
+  }
+}
+
 gc_status dalloc(DeviceBuffer &b, size_t bytes) {
   if (bytes == 0) bytes = 256;
   if (b.ptr && b.bytes >= bytes) return GC_OK;
@@ -243,7 +251,7 @@ extern "C" const char *gc_status_str(gc_status status) {
     case GC_EINVAL: return "GC_EINVAL: invalid argument";
     case GC_ERANGE: return "GC_ERANGE: vertex id out of range";
     case GC_ECAPACITY: return "GC_ECAPACITY: output buffer too small";
-    case GC_ENOMEM: return "GC_ENOMEM: device allocation failed";
+    case GC_ENOMEM: return "GC_ENOMEM: device or host allocation failed";
     case GC_EDEVICE: return "GC_EDEVICE: HIP runtime error";
     case GC_EOVERFLOW: return "GC_EOVERFLOW: size beyond the library's limits";
     default: return "unknown gc_status";

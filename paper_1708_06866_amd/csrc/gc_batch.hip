@@ -173,7 +173,11 @@ extern "C" gc_status gc_batch_build(const int32_t *d_src, const int32_t *d_dst,
     set_error("gc_batch_build: invalid argument");
     return GC_EINVAL;
   }
-  std::vector<int32_t> vbase(G + 1, 0);
+  std::vector<int32_t> vbase;
+  GC_TRY(guard_host("gc_batch_build", [&]() -> gc_status {
+    vbase.assign((size_t)G + 1, 0);
+    return GC_OK;
+  }));
   int64_t nsum = 0;
   for (int32_t i = 0; i < G; ++i) {
     if (h_nv[i] < 0 || h_pair_off[i + 1] < h_pair_off[i] || (i == 0 && h_pair_off[0] != 0)) {
@@ -206,6 +210,11 @@ extern "C" gc_status gc_batch_build(const int32_t *d_src, const int32_t *d_dst,
     return st;
   };
   if (hipGetDevice(&b->device) != hipSuccess) return fail(GC_EDEVICE);
+  const gc_status hs = guard_host("gc_batch_build", [&]() -> gc_status {
+    b->edge_off.assign((size_t)G + 1, 0);
+    return GC_OK;
+  });
+  if (hs != GC_OK) return fail(hs);
   DeviceBuffer d_off, d_shift, d_err;
   struct Cleanup {
     DeviceBuffer *a, *b, *c;
@@ -253,7 +262,6 @@ extern "C" gc_status gc_batch_build(const int32_t *d_src, const int32_t *d_dst,
   k_edge_offsets<<<gsz((int64_t)G + 1), 256, 0, s>>>(static_cast<const int32_t *>(g->u.ptr), g->m,
                                                      static_cast<const int32_t *>(b->vbase.ptr), G,
                                                      static_cast<int64_t *>(d_off.ptr));
-  b->edge_off.assign(G + 1, 0);
   if (hipMemcpyAsync(b->edge_off.data(), d_off.ptr, sizeof(int64_t) * (G + 1),
                      hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <exception>
 #include <string>
 
 #include "gc.h"
@@ -38,6 +39,23 @@ void clear_error();
 
 // Check the last kernel launch.
 #define GC_LAUNCH_CHECK() GC_HIP(hipGetLastError())
+
+// Entry points that allocate host memory or start threads keep C++ exceptions
+// from crossing the C ABI: a failed host allocation or thread start becomes
+// GC_ENOMEM, with the exception's text as the last error.
+void note_host_failure(const char *where, const char *what) noexcept;
+
+template <class F>
+inline gc_status guard_host(const char *where, F &&body) noexcept {
+  try {
+    return body();
+  } catch (const std::exception &e) {
+    note_host_failure(where, e.what());
+  } catch (...) {
+    note_host_failure(where, "unknown exception");
+  }
+  return GC_ENOMEM;
+}
 
 // --------------------------------------------------------------------------
 // Device memory: a tracked allocation and a grow-only bump workspace.

@@ -93,6 +93,26 @@ std::vector<const char *> chunks(const char *b, const char *e, int parts) {
   return cut;
 }
 
+// Run fn(i) for every chunk i < nc: chunk 0 on the calling thread, the others
+// on threads of their own.  A thread that cannot start (too many threads, no
+// address space for its stack) leaves its chunk to the calling thread.
+template <class F>
+void run_chunks(int nc, F &&fn) {
+  std::vector<std::thread> th;
+  int started = 1;  // chunks [1, started) run on threads
+  try {
+    th.reserve((size_t)std::max(nc - 1, 0));
+    for (int i = 1; i < nc; ++i) {
+      th.emplace_back(fn, i);
+      started = i + 1;
+    }
+  } catch (const std::exception &) {
+  }
+  for (int i = started; i < nc; ++i) fn(i);
+  if (nc > 0) fn(0);
+  for (auto &t : th) t.join();
+}
+
 struct ChunkOut {
   int64_t lines = 0;
   uint64_t max_id = 0;
@@ -102,10 +122,8 @@ struct ChunkOut {
 
 }  // namespace
 
-extern "C" gc_status gc_read_edges(const char *path, int32_t format, int32_t *h_src,
-                                   int32_t *h_dst, int64_t cap, int64_t *n_pairs,
-                                   int64_t *n_vertices) {
-  gc::clear_error();
+static gc_status read_edges(const char *path, int32_t format, int32_t *h_src, int32_t *h_dst,
+                            int64_t cap, int64_t *n_pairs, int64_t *n_vertices) {
   if (!path || !n_pairs || (format != GC_FILE_AUTO && format != GC_FILE_TSV &&
                             format != GC_FILE_MMIO) ||
       ((h_src == nullptr) != (h_dst == nullptr))) {
@@ -198,12 +216,7 @@ extern "C" gc_status gc_read_edges(const char *path, int32_t format, int32_t *h_
     }
     co[i].lines = k;
   };
-  {
-    std::vector<std::thread> th;
-    for (int i = 1; i < nc; ++i) th.emplace_back(count, i);
-    if (nc > 0) count(0);
-    for (auto &t : th) t.join();
-  }
+  run_chunks(nc, count);
   std::vector<int64_t> off(nc + 1, 0);
   for (int i = 0; i < nc; ++i) off[i + 1] = off[i] + co[i].lines;
   const int64_t total = off[nc];
@@ -252,12 +265,7 @@ extern "C" gc_status gc_read_edges(const char *path, int32_t format, int32_t *h_
     }
     co[i].max_id = mx;
   };
-  {
-    std::vector<std::thread> th;
-    for (int i = 1; i < nc; ++i) th.emplace_back(parse, i);
-    if (nc > 0) parse(0);
-    for (auto &t : th) t.join();
-  }
+  run_chunks(nc, parse);
   uint64_t mx = 0;
   for (int i = 0; i < nc; ++i) {
     if (co[i].st != GC_OK) {
@@ -273,4 +281,26 @@ extern "C" gc_status gc_read_edges(const char *path, int32_t format, int32_t *h_
   }
   if (n_vertices) *n_vertices = mmio ? (int64_t)std::max(mm_rows, mm_cols) : (int64_t)mx;
   return GC_OK;
+}
+
+extern "C" gc_status gc_read_edges(const char *path, int32_t format, int32_t *h_src,
+                                   int32_t *h_dst, int64_t cap, int64_t *n_pairs,
+                                   int64_t *n_vertices) {
+  gc::clear_error();
+  // no C++ exception may cross the C ABI: a failed host allocation becomes a
+  // status (threads that cannot start are handled inside, by run_chunks)
+  try {
+    return read_edges(path, format, h_src, h_dst, cap, n_pairs, n_vertices);
+  } catch (const std::exception &e) {
+    try {
+      set_error(std::string("gc_read_edges: host allocation failed: ") + e.what());
+    } catch (...) {
+    }
+  } catch (...) {
+    try {
+      set_error("gc_read_edges: unknown exception");
+    } catch (...) {
+    }
+  }
+  return GC_ENOMEM;
 }

@@ -377,8 +377,16 @@ extern "C" gc_status gc_server_create(int64_t budget_bytes, gc_server **out) {
     gc_server_destroy(sv);
     return GC_EDEVICE;
   }
-  sv->sched = std::thread(scheduler_loop, sv);
-  sv->worker = std::thread(truss_loop, sv);
+  // a thread that cannot start: stop and join the one that did, then free
+  const gc_status st = guard_host("gc_server_create", [&]() -> gc_status {
+    sv->sched = std::thread(scheduler_loop, sv);
+    sv->worker = std::thread(truss_loop, sv);
+    return GC_OK;
+  });
+  if (st != GC_OK) {
+    gc_server_destroy(sv);
+    return st;
+  }
   *out = sv;
   return GC_OK;
 }
@@ -406,18 +414,20 @@ extern "C" gc_status gc_server_add_graph(gc_server *sv, const int32_t *h_src, co
       set_error("gc_server_add_graph: vertex id outside [0, n_vertices)");
       return GC_ERANGE;
     }
-  gc_server_graph G;
-  G.src.assign(h_src, h_src + n_pairs);
-  G.dst.assign(h_dst, h_dst + n_pairs);
-  G.n = n_vertices;
-  std::lock_guard<std::mutex> g(sv->mu);
-  if (build_peak_bytes(n_pairs, n_vertices) > sv->budget) {
-    set_error("gc_server_add_graph: graph cannot fit in the server's memory budget");
-    return GC_ENOMEM;
-  }
-  *graph_id = (int32_t)sv->graphs.size();
-  sv->graphs.push_back(std::move(G));
-  return GC_OK;
+  return guard_host("gc_server_add_graph", [&]() -> gc_status {
+    gc_server_graph G;
+    G.src.assign(h_src, h_src + n_pairs);
+    G.dst.assign(h_dst, h_dst + n_pairs);
+    G.n = n_vertices;
+    std::lock_guard<std::mutex> g(sv->mu);
+    if (build_peak_bytes(n_pairs, n_vertices) > sv->budget) {
+      set_error("gc_server_add_graph: graph cannot fit in the server's memory budget");
+      return GC_ENOMEM;
+    }
+    *graph_id = (int32_t)sv->graphs.size();
+    sv->graphs.push_back(std::move(G));
+    return GC_OK;
+  });
 }
 
 extern "C" gc_status gc_server_submit(gc_server *sv, const gc_request *req, int64_t *ticket) {
@@ -427,22 +437,29 @@ extern "C" gc_status gc_server_submit(gc_server *sv, const gc_request *req, int6
     set_error("gc_server_submit: invalid argument");
     return GC_EINVAL;
   }
-  std::lock_guard<std::mutex> g(sv->mu);
-  if (req->graph_id < 0 || req->graph_id >= (int32_t)sv->graphs.size()) {
-    set_error("gc_server_submit: unknown graph id");
-    return GC_EINVAL;
-  }
-  gc_server_req r;
-  r.ticket = sv->next_ticket++;
-  r.graph_id = req->graph_id;
-  r.kind = req->kind;
-  r.k = req->k;
-  r.t_submit = now_s();
-  sv->reqs[r.ticket] = r;
-  sv->pending.push_back(r.ticket);
-  *ticket = r.ticket;
-  sv->cv.notify_one();
-  return GC_OK;
+  return guard_host("gc_server_submit", [&]() -> gc_status {
+    std::lock_guard<std::mutex> g(sv->mu);
+    if (req->graph_id < 0 || req->graph_id >= (int32_t)sv->graphs.size()) {
+      set_error("gc_server_submit: unknown graph id");
+      return GC_EINVAL;
+    }
+    gc_server_req r;
+    r.ticket = sv->next_ticket++;
+    r.graph_id = req->graph_id;
+    r.kind = req->kind;
+    r.k = req->k;
+    r.t_submit = now_s();
+    auto it = sv->reqs.emplace(r.ticket, r).first;
+    try {
+      sv->pending.push_back(r.ticket);
+    } catch (...) {
+      sv->reqs.erase(it);  // not queued: forget it, so no wait() can block on it
+      throw;
+    }
+    *ticket = r.ticket;
+    sv->cv.notify_one();
+    return GC_OK;
+  });
 }
 
 static gc_status take_result(gc_server *sv, int64_t ticket, gc_result *out) {

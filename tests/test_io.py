@@ -118,3 +118,50 @@ def test_table2_king_graph_from_tsv(tmp_path):
     u, v = oracle.normalise(s2, d2, n2)
     assert len(u) == 260610
     assert oracle.triangle_count(n2, u, v) == 4 * 255 ** 2
+
+
+_NO_THREAD_CHILD = r"""
+import ctypes, resource, sys
+import numpy as np
+import paper_1708_06866_amd as gc
+
+path = sys.argv[1]
+L = gc.lib()
+src0, dst0, n0 = gc.gc_read_edges(path)        # unconstrained read
+src = np.zeros_like(src0)
+dst = np.zeros_like(dst0)
+n_pairs, n_vertices = ctypes.c_int64(0), ctypes.c_int64(0)
+vm = [int(l.split()[1]) * 1024 for l in open("/proc/self/status") if l.startswith("VmSize:")][0]
+soft, hard = resource.getrlimit(resource.RLIMIT_AS)
+# room for the file mapping, but not for the worker threads' 8 MiB stacks
+resource.setrlimit(resource.RLIMIT_AS, (vm + (12 << 20), hard))
+st = L.gc_read_edges(path.encode(), gc.GC_FILE_AUTO, src.ctypes.data_as(ctypes.c_void_p),
+                     dst.ctypes.data_as(ctypes.c_void_p), len(src), ctypes.byref(n_pairs),
+                     ctypes.byref(n_vertices))
+resource.setrlimit(resource.RLIMIT_AS, (soft, hard))
+assert st == gc.GC_OK, st
+assert n_pairs.value == len(src0) and n_vertices.value == n0
+assert np.array_equal(src, src0) and np.array_equal(dst, dst0)
+print("ok", len(src0))
+"""
+
+
+def test_reader_survives_threads_that_cannot_start(tmp_path):
+    """With no address space left for thread stacks, a multi-chunk read runs
+    its chunks on the calling thread and returns every pair (no C++
+    exception escapes the C ABI to abort the process)."""
+    import subprocess
+    import sys
+    src, dst, n = gg.rmat(14, 16, seed=4)
+    p = os.path.join(tmp_path, "r14.tsv")
+    write_tsv(p, src, dst)
+    assert os.path.getsize(p) > 2 << 20           # several chunks
+    child = os.path.join(tmp_path, "child.py")
+    with open(child, "w") as f:
+        f.write(_NO_THREAD_CHILD)
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, PYTHONPATH=root)
+    r = subprocess.run([sys.executable, child, p], env=env, capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode == 0, (r.returncode, r.stderr[-2000:])
+    assert r.stdout.split() == ["ok", str(len(src))]
