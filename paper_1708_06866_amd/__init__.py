@@ -158,6 +158,37 @@ def _dev_i32(t: torch.Tensor, name: str) -> torch.Tensor:
     return t.contiguous()
 
 
+def _dev_out(t, dtype: torch.dtype, need: int, name: str, device: torch.device) -> torch.Tensor:
+    """A caller-supplied output that the kernels write in place: a contiguous
+    cuda tensor of ``dtype`` with at least ``need`` entries on ``device``.
+    Checked before any library call, so a wrong buffer raises here instead
+    of reaching a kernel."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, not %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if t.numel() < need:
+        raise ValueError("%s holds %d entries, %d needed" % (name, t.numel(), need))
+    if t.device.type != "cuda" or (device is not None and t.device != device):
+        raise TypeError("%s must be a cuda tensor on %s, not on %s" % (name, device, t.device))
+    return t
+
+
+def _host_ids(a, name: str):
+    """Host or device integer ids -> int32 tensor; ids that do not fit int32
+    raise instead of wrapping."""
+    t = torch.as_tensor(a)
+    if t.dtype == torch.int32:
+        return t
+    if t.dtype.is_floating_point or t.dtype.is_complex or t.dtype == torch.bool:
+        raise TypeError("%s must hold integer ids, not %s" % (name, t.dtype))
+    if t.numel() and (int(t.min()) < -(1 << 31) or int(t.max()) >= (1 << 31)):
+        raise ValueError("%s holds ids outside int32" % name)
+    return t.to(torch.int32)
+
+
 def _ptr(t: torch.Tensor):
     return ctypes.c_void_p(t.data_ptr())
 
@@ -297,6 +328,8 @@ def gc_triangle_count(g: Graph, stream=None) -> int:
 
 
 def gc_edge_support(g: Graph, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    if out is not None:
+        _dev_out(out, torch.int32, 0, "out", g.device)
     _, m, _ = g.info()
     if out is None:
         out = torch.empty(max(m, 1), dtype=torch.int32, device=g.device)
@@ -306,6 +339,8 @@ def gc_edge_support(g: Graph, out: torch.Tensor | None = None, stream=None) -> t
 
 
 def gc_ktruss(g: Graph, k: int, out: torch.Tensor | None = None, stream=None):
+    if out is not None:
+        _dev_out(out, torch.uint8, 0, "out", g.device)
     _, m, _ = g.info()
     if out is None:
         out = torch.empty(max(m, 1), dtype=torch.uint8, device=g.device)
@@ -316,6 +351,8 @@ def gc_ktruss(g: Graph, k: int, out: torch.Tensor | None = None, stream=None):
 
 
 def gc_truss_decomposition(g: Graph, out: torch.Tensor | None = None, stream=None):
+    if out is not None:
+        _dev_out(out, torch.int32, 0, "out", g.device)
     _, m, _ = g.info()
     if out is None:
         out = torch.empty(max(m, 1), dtype=torch.int32, device=g.device)
@@ -327,8 +364,8 @@ def gc_truss_decomposition(g: Graph, out: torch.Tensor | None = None, stream=Non
 
 def build_graph(src, dst, n_vertices: int, device="cuda", one_based: bool = False) -> Graph:
     """Convenience: host or device int32 pairs -> Graph on ``device``."""
-    s = torch.as_tensor(src, dtype=torch.int32).to(device)
-    d = torch.as_tensor(dst, dtype=torch.int32).to(device)
+    s = _host_ids(src, "src").to(device)
+    d = _host_ids(dst, "dst").to(device)
     return gc_build_csr(s, d, n_vertices, GC_INPUT_ONE_BASED if one_based else 0)
 
 
@@ -409,6 +446,9 @@ class Batch:
         return g
 
     def triangle_count(self, out=None, stream=None) -> torch.Tensor:
+        # the C call has no capacity argument: out must hold one count per graph
+        if out is not None:
+            _dev_out(out, torch.int64, self.n_graphs, "out", self.device)
         if out is None:
             out = torch.empty(max(self.n_graphs, 1), dtype=torch.int64, device=self.device)
         _check(lib().gc_batch_triangle_count(self.handle, _ptr(out), _stream(stream)),
@@ -417,6 +457,8 @@ class Batch:
 
     def edge_support(self, out=None, stream=None) -> torch.Tensor:
         m = int(self.edge_offsets[-1])
+        if out is not None:
+            _dev_out(out, torch.int32, 0, "out", self.device)
         if out is None:
             out = torch.empty(max(m, 1), dtype=torch.int32, device=self.device)
         _check(lib().gc_batch_edge_support(self.handle, _ptr(out), out.numel(), _stream(stream)),
@@ -466,8 +508,8 @@ def gc_batch_build(src: torch.Tensor, dst: torch.Tensor, pair_offsets, n_vertice
 
 def build_batch(graphs, device="cuda") -> Batch:
     """Convenience: list of host (src, dst, n) -> Batch on ``device``."""
-    srcs = [_np.asarray(g[0], dtype=_np.int32) for g in graphs]
-    dsts = [_np.asarray(g[1], dtype=_np.int32) for g in graphs]
+    srcs = [_host_ids(g[0], "src").cpu().numpy().reshape(-1) for g in graphs]
+    dsts = [_host_ids(g[1], "dst").cpu().numpy().reshape(-1) for g in graphs]
     off = _np.zeros(len(graphs) + 1, dtype=_np.int64)
     off[1:] = _np.cumsum([len(x) for x in srcs])
     nv = [int(g[2]) for g in graphs]
@@ -518,8 +560,10 @@ class Server:
         _check(lib().gc_server_set_mode(self.handle, int(mode)), "gc_server_set_mode")
 
     def add_graph(self, src, dst, n_vertices: int) -> int:
-        s = _np.ascontiguousarray(src, dtype=_np.int32)
-        d = _np.ascontiguousarray(dst, dtype=_np.int32)
+        s = _np.ascontiguousarray(_host_ids(src, "src").cpu().numpy().reshape(-1))
+        d = _np.ascontiguousarray(_host_ids(dst, "dst").cpu().numpy().reshape(-1))
+        if len(s) != len(d):
+            raise ValueError("src and dst differ in length")
         gid = ctypes.c_int32()
         _check(lib().gc_server_add_graph(self.handle, ctypes.c_void_p(s.ctypes.data),
                                          ctypes.c_void_p(d.ctypes.data), len(s), int(n_vertices),

@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -117,3 +118,73 @@ def test_null_handles_rejected_on_the_host(lib):
         f.argtypes = [P]
         f.restype = None
         f(None)
+
+
+@pytest.fixture
+def no_library(monkeypatch):
+    """The binding with its library replaced by a tripwire: any call into
+    libgc fails the test, so a check that passes here ran on the host first."""
+    import paper_1708_06866_amd as gc
+
+    def tripwire():
+        raise AssertionError("the library was called")
+    monkeypatch.setattr(gc, "lib", tripwire)
+    return gc
+
+
+def test_output_buffers_checked_before_any_library_call(no_library):
+    """Caller-supplied outputs are written in place by the kernels: wrong
+    dtype, layout, length or device is refused by the binding."""
+    import torch
+    gc = no_library
+
+    class NoGraph(gc.Graph):
+        def info(self):
+            raise AssertionError("the handle was queried")
+    g = NoGraph(ctypes.c_void_p(None), torch.device("cuda", 0))
+    cases = (
+        (gc.gc_edge_support, torch.int32), (gc.gc_truss_decomposition, torch.int32),
+        (lambda g_, out: gc.gc_ktruss(g_, 3, out), torch.uint8))
+    for call, dtype in cases:
+        other = torch.int64 if dtype != torch.int64 else torch.int32
+        with pytest.raises(TypeError):
+            call(g, [0] * 8)                                      # not a tensor
+        with pytest.raises(TypeError):
+            call(g, torch.zeros(8, dtype=other))                  # wrong dtype
+        with pytest.raises(ValueError):
+            call(g, torch.zeros(8, 2, dtype=dtype)[:, 0])         # strided view
+        with pytest.raises(TypeError):
+            call(g, torch.zeros(8, dtype=dtype))                  # host memory
+
+    b = gc.Batch.__new__(gc.Batch)
+    b._h, b.device, b.n_graphs = ctypes.c_void_p(None), torch.device("cuda", 0), 5
+    b.edge_offsets = np.zeros(6, np.int64)
+    with pytest.raises(ValueError):
+        b.triangle_count(out=torch.zeros(4, dtype=torch.int64))   # one short
+    with pytest.raises(TypeError):
+        b.triangle_count(out=torch.zeros(5, dtype=torch.int64))   # host memory
+    with pytest.raises(TypeError):
+        b.edge_support(out=torch.zeros(5, dtype=torch.int64))     # wrong dtype
+
+
+def test_host_inputs_checked_before_any_library_call(no_library):
+    """Host pair arrays: unequal lengths and ids beyond int32 are refused
+    instead of being read past the end or wrapped."""
+    import torch
+    gc = no_library
+    srv = gc.Server.__new__(gc.Server)
+    srv._h = ctypes.c_void_p(None)
+    with pytest.raises(ValueError):
+        srv.add_graph(np.array([0, 1, 2], np.int32), np.array([1, 2], np.int32), 3)
+    with pytest.raises(ValueError):
+        srv.add_graph(np.array([0, 1 << 31], np.int64), np.array([1, 2], np.int64), 3)
+    with pytest.raises(TypeError):
+        srv.add_graph(np.array([0.0, 1.0]), np.array([1.0, 2.0]), 3)
+    with pytest.raises(ValueError):
+        gc.build_graph(np.array([-(1 << 31) - 1], np.int64), np.array([0], np.int64), 1,
+                       device="cpu")
+    # in-range ids of any integer type arrive as int32, unchanged
+    t = gc._host_ids(np.array([0, 5, (1 << 31) - 1], np.int64), "src")
+    assert t.dtype == torch.int32 and t.tolist() == [0, 5, (1 << 31) - 1]
+    a = np.array([3, 1], np.int32)
+    assert np.shares_memory(gc._host_ids(a, "src").numpy(), a)
