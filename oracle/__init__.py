@@ -43,11 +43,15 @@ def build(force: bool = True) -> str:
 
 
 def _load():
+    """Load ``liboracle.so``; the environment variable ORACLE_LIB names another
+    build of ``oracle.c`` instead (the mutation tests load planted mistakes
+    this way, to show that the pins catch them)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH):
+        path = os.environ.get("ORACLE_LIB") or _LIB_PATH
+        if path == _LIB_PATH and not os.path.exists(_LIB_PATH):
             build(force=False)
-        lib = ctypes.CDLL(_LIB_PATH)
+        lib = ctypes.CDLL(path)
         P = ctypes.c_void_p
         i32, i64 = ctypes.c_int32, ctypes.c_int64
         lib.oracle_normalise.argtypes = [P, P, i64, i32, i32, P, P]

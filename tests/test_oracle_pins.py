@@ -192,6 +192,33 @@ def test_exhaustive_five_vertices_ktruss_vs_subset_enumeration():
             assert np.array_equal(bulk, want) and np.array_equal(peel, want)
 
 
+def test_five_vertices_decomposition_vs_subset_enumeration():
+    """Truss numbers (Sec. III-B, last paragraph: the k-truss for growing k
+    until it is empty) against the definition: tau(e) is the largest k whose
+    maximal k-truss, enumerated over every edge subset, holds e; kmax is the
+    largest tau (0 without edges, reading R2).  160 graphs on 5 vertices and
+    K_5 itself, by both oracle methods."""
+    nv = 5
+    pairs = _all_graphs_on(nv)
+    all_u = np.array([p[0] for p in pairs], np.int32)
+    all_v = np.array([p[1] for p in pairs], np.int32)
+    rng = np.random.default_rng(11)
+    graphs = list(rng.choice(1 << len(pairs), 160, replace=False)) + [(1 << len(pairs)) - 1, 0]
+    for g in graphs:
+        sel = ((int(g) >> np.arange(len(pairs))) & 1).astype(bool)
+        u, v = all_u[sel], all_v[sel]
+        want = np.full(len(u), 2, np.int32)
+        for k in (3, 4, 5, 6):
+            want[dense.brute_ktruss(nv, u, v, k).astype(bool)] = k
+        want_kmax = int(want.max()) if len(u) else 0
+        if sel.all():                                   # K_5: every edge in 3 triangles
+            assert want_kmax == 5 and (want == 5).all()
+        for method in ("peel", "bulk"):
+            tau, kmax = oracle.truss_decomposition(nv, u, v, method)
+            assert np.array_equal(tau, want), (int(g), method)
+            assert kmax == want_kmax, (int(g), method)
+
+
 # --------------------------------------------------------------------------
 # support vs Alg. 2's C(u,v) and Alg. 4's (EA == 2) 1
 # --------------------------------------------------------------------------
