@@ -587,8 +587,8 @@ def main():
     # they move fewer bytes than B_TC -- that tighter count is reported beside
     tc_bytes = ab["B_model_min"]
     achieved = tc_bytes / (tc_ms / 1000.0) / 1e9
-    stream = stream_bandwidth(torch, dev)
-    log("achievable bandwidth: copy %.0f GB/s (read + write)" % stream["copy_GBps"])
+    bw = stream_bandwidth(torch, dev)
+    log("achievable bandwidth: copy %.0f GB/s (read + write)" % bw["copy_GBps"])
     achieved_tail = ab["bytes"] / (tc_ms / 1000.0) / 1e9
     out = {
         "metric": "triangle-count and k-truss edges/sec at R-MAT scale 24",
@@ -650,8 +650,8 @@ def main():
             "tail_model_bytes": ab["bytes"], "achieved_tail_model": achieved_tail,
             "frac_tail_model": achieved_tail / HBM_PEAK_GBS, "probes": ab["probes"],
             "pass_ms": tc_ms,
-            "achievable_copy_GBps": stream["copy_GBps"],
-            "frac_of_achievable_copy": achieved / stream["copy_GBps"],
+            "achievable_copy_GBps": bw["copy_GBps"],
+            "frac_of_achievable_copy": achieved / bw["copy_GBps"],
         },
     }
     if args.batch_graphs > 0:
