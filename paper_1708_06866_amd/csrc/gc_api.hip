@@ -186,7 +186,8 @@ extern "C" gc_status gc_graph_truss_stats(const gc_graph *g, int64_t *h_stats, i
     set_error("gc_graph_truss_stats: invalid argument");
     return GC_EINVAL;
   }
-  for (int32_t i = 0; i < cap && i < 41; ++i) h_stats[i] = g->peel_stats[i];
+  constexpr int32_t kStats = (int32_t)(sizeof(g->peel_stats) / sizeof(g->peel_stats[0]));
+  for (int32_t i = 0; i < cap && i < kStats; ++i) h_stats[i] = g->peel_stats[i];
   return GC_OK;
 }
 
