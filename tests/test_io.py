@@ -165,3 +165,49 @@ def test_reader_survives_threads_that_cannot_start(tmp_path):
                        timeout=300)
     assert r.returncode == 0, (r.returncode, r.stderr[-2000:])
     assert r.stdout.split() == ["ok", str(len(src))]
+
+
+def _reference_tsv(text: str):
+    """Plain reading of the TSV rules: skip blank and '#'/'%' lines, take the
+    first two fields of every other line as 1-based ids."""
+    src, dst = [], []
+    for line in text.split("\n"):
+        f = line.replace("\r", " ").split()
+        if not f or f[0][0] in "#%":
+            continue
+        src.append(int(f[0]) - 1)
+        dst.append(int(f[1]) - 1)
+    return np.array(src, np.int32), np.array(dst, np.int32)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_chunked_read_matches_a_plain_parser(tmp_path, seed):
+    """Files a little above the multi-chunk threshold, with comments, blank
+    lines, CRLF ends, runs of blanks and long lines falling on chunk cuts,
+    read exactly as a line-by-line parser reads them."""
+    rng = np.random.default_rng(seed)
+    lines, size = [], 0
+    while size < (1 << 20) + 300_000:
+        r = rng.random()
+        if r < 0.05:
+            s = "# " + "c" * int(rng.integers(0, 3000))       # long comment
+        elif r < 0.08:
+            s = "% note"
+        elif r < 0.11:
+            s = " " * int(rng.integers(0, 4))                  # blank
+        else:
+            u, v = rng.integers(1, 1 << 20, 2)
+            sep = [" ", "\t", "  ", " \t "][int(rng.integers(0, 4))]
+            tail = ["", "\t1", " 7", "\t1.5"][int(rng.integers(0, 4))]
+            s = " " * int(rng.integers(0, 2)) + "%d%s%d%s" % (u, sep, v, tail)
+        end = "\r\n" if rng.random() < 0.3 else "\n"
+        lines.append(s + end)
+        size += len(s) + len(end)
+    if rng.random() < 0.5:
+        lines[-1] = lines[-1].rstrip("\r\n")                   # no final newline
+    text = "".join(lines)
+    p = write(tmp_path, "mixed.tsv", text)
+    s_ref, d_ref = _reference_tsv(text)
+    s2, d2, n2 = gc.gc_read_edges(p)
+    assert np.array_equal(s2, s_ref) and np.array_equal(d2, d_ref)
+    assert n2 == int(max(s_ref.max(), d_ref.max())) + 1
