@@ -202,14 +202,20 @@ extern "C" gc_status gc_batch_build(const int32_t *d_src, const int32_t *d_dst,
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
   gc_batch *b = new (std::nothrow) gc_batch();
-  if (!b) return GC_ENOMEM;
+  if (!b) {
+    set_error("gc_batch_build: host allocation of the handle failed");
+    return GC_ENOMEM;
+  }
   b->G = G;
   b->pairs = P;
   auto fail = [&](gc_status st) {
     gc_batch_free(b);
     return st;
   };
-  if (hipGetDevice(&b->device) != hipSuccess) return fail(GC_EDEVICE);
+  if (hipGetDevice(&b->device) != hipSuccess) {
+    set_error("gc_batch_build: hipGetDevice failed");
+    return fail(GC_EDEVICE);
+  }
   const gc_status hs = guard_host("gc_batch_build", [&]() -> gc_status {
     b->edge_off.assign((size_t)G + 1, 0);
     return GC_OK;

@@ -320,7 +320,10 @@ extern "C" gc_status gc_build_csr(const int32_t *d_src, const int32_t *d_dst, in
     return GC_ERANGE;
   }
   gc_graph *g = new (std::nothrow) gc_graph();
-  if (!g) return GC_ENOMEM;
+  if (!g) {
+    gc::set_error("gc_build_csr: host allocation of the handle failed");
+    return GC_ENOMEM;
+  }
   g->n = n_vertices;
   hipError_t e = hipGetDevice(&g->device);
   if (e != hipSuccess) {

@@ -366,7 +366,10 @@ extern "C" gc_status gc_server_create(int64_t budget_bytes, gc_server **out) {
   }
   *out = nullptr;
   gc_server *sv = new (std::nothrow) gc_server();
-  if (!sv) return GC_ENOMEM;
+  if (!sv) {
+    set_error("gc_server_create: host allocation of the handle failed");
+    return GC_ENOMEM;
+  }
   sv->budget = budget_bytes;
   if (hipGetDevice(&sv->device) != hipSuccess ||
       hipStreamCreateWithFlags(&sv->s_count, hipStreamNonBlocking) != hipSuccess ||
