@@ -188,3 +188,51 @@ def test_host_inputs_checked_before_any_library_call(no_library):
     assert t.dtype == torch.int32 and t.tolist() == [0, 5, (1 << 31) - 1]
     a = np.array([3, 1], np.int32)
     assert np.shares_memory(gc._host_ids(a, "src").numpy(), a)
+
+
+C_CONSUMER = r"""
+#include <stdio.h>
+#include <string.h>
+#include "gc.h"
+
+int main(int argc, char **argv) {
+  /* host-only calls: no GPU is touched */
+  if (argc != 2) return 4;
+  int64_t n_pairs = 0, n_vertices = 0;
+  gc_status st = gc_read_edges(argv[1], GC_FILE_AUTO, NULL, NULL, 0, &n_pairs, &n_vertices);
+  if (st != GC_OK) { printf("size query failed: %s\n", gc_last_error()); return 1; }
+  int32_t src[8], dst[8];
+  st = gc_read_edges(argv[1], GC_FILE_TSV, src, dst, 8, &n_pairs, &n_vertices);
+  if (st != GC_OK || n_pairs != 3 || n_vertices != 4) return 2;
+  printf("pairs %lld n %lld first %d-%d\n", (long long)n_pairs, (long long)n_vertices,
+         src[0], dst[0]);
+  gc_graph *g = (gc_graph *)1;
+  st = gc_build_csr(NULL, NULL, 5, 4, 0, NULL, &g);   /* NULL pairs with n_pairs > 0 */
+  printf("build %d %s g=%p\n", (int)st, gc_status_str(st), (void *)g);
+  printf("error '%s'\n", gc_last_error());
+  gc_graph_free(NULL);
+  return st == GC_EINVAL && g == NULL && strlen(gc_last_error()) > 0 ? 0 : 3;
+}
+"""
+
+
+def test_header_is_plain_c_and_links(tmp_path):
+    """include/gc.h compiles as C99 with warnings as errors, and a C program
+    linked against libgc.so calls its host-only entry points."""
+    import subprocess
+    if not os.path.exists(LIB):
+        from paper_1708_06866_amd import build
+        build.build()
+    c = tmp_path / "consumer.c"
+    c.write_text(C_CONSUMER)
+    exe = tmp_path / "consumer"
+    libdir = os.path.dirname(LIB)
+    subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Wextra", "-Werror", "-pedantic",
+                           "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe),
+                           LIB, "-Wl,-rpath," + libdir])
+    tsv = tmp_path / "e.tsv"
+    tsv.write_text("1\t2\t1\n2\t3\t1\n4\t1\t1\n")
+    r = subprocess.run([str(exe), str(tsv)], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, (r.returncode, r.stdout, r.stderr)
+    assert "pairs 3 n 4 first 0-1" in r.stdout
+    assert "build -1 GC_EINVAL" in r.stdout and "g=(nil)" in r.stdout
