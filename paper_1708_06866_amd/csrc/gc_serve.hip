@@ -135,11 +135,10 @@ static bool make_room(gc_server *sv, int64_t need) {
 // Build graph `id` (called with the lock released; `building` set by caller).
 static gc_status build_graph(gc_server *sv, gc_server_graph &G) {
   const int64_t P = (int64_t)G.src.size();
-  DeviceBuffer ds, dd;
-  GC_TRY(dalloc(ds, sizeof(int32_t) * (size_t)(P + 1)));
-  GC_TRY(dalloc(dd, sizeof(int32_t) * (size_t)(P + 1)));
-  gc_status st = GC_OK;
-  if (P > 0) {
+  DeviceBuffer ds, dd;  // freed below on every path
+  gc_status st = dalloc(ds, sizeof(int32_t) * (size_t)(P + 1));
+  if (st == GC_OK) st = dalloc(dd, sizeof(int32_t) * (size_t)(P + 1));
+  if (st == GC_OK && P > 0) {
     if (hipMemcpyAsync(ds.ptr, G.src.data(), sizeof(int32_t) * P, hipMemcpyHostToDevice,
                        sv->s_build) != hipSuccess ||
         hipMemcpyAsync(dd.ptr, G.dst.data(), sizeof(int32_t) * P, hipMemcpyHostToDevice,
@@ -286,11 +285,18 @@ static void scheduler_loop(gc_server *sv) {
   std::unique_lock<std::mutex> lk(sv->mu);
   while (!sv->stop) {
     bool progressed = false;
-    // complete the running batch
-    if (sv->batch_running && hipEventQuery(sv->batch_done) == hipSuccess) {
+    // complete the running batch (a failed batch fails its requests rather
+    // than leaving them pending for ever)
+    const hipError_t q = sv->batch_running ? hipEventQuery(sv->batch_done) : hipErrorNotReady;
+    if (sv->batch_running && q != hipErrorNotReady) {
       progressed = true;
+      if (q != hipSuccess) {
+        (void)hipGetLastError();
+        sv->error = std::string("count batch: ") + hipGetErrorString(q);
+      }
       for (size_t i = 0; i < sv->batch.size(); ++i)
-        finish(sv, sv->reqs[sv->batch[i]], GC_OK, (int64_t)sv->h_out[i]);
+        finish(sv, sv->reqs[sv->batch[i]], q == hipSuccess ? GC_OK : GC_EDEVICE,
+               q == hipSuccess ? (int64_t)sv->h_out[i] : 0);
       sv->batch.clear();
       sv->batch_g.clear();
       sv->batch_running = false;
