@@ -176,10 +176,13 @@ static gc_status decomposition_impl(gc_graph *g, int32_t *truss, int32_t *h_kmax
   }
   GC_TRY(truss_state_alloc(g));
   int32_t *tau = truss;
-  DeviceBuffer own;
+  struct Owned {  // truss numbers when the caller passes none, freed on every return
+    DeviceBuffer b;
+    ~Owned() { dfree(b); }
+  } own;
   if (!tau) {
-    GC_TRY(dalloc(own, sizeof(int32_t) * (size_t)m));
-    tau = static_cast<int32_t *>(own.ptr);
+    GC_TRY(dalloc(own.b, sizeof(int32_t) * (size_t)m));
+    tau = static_cast<int32_t *>(own.b.ptr);
   }
   k_fill_i32<<<gsz(m), 256, 0, s>>>(tau, m, 2);
   GC_LAUNCH_CHECK();
@@ -219,7 +222,6 @@ static gc_status decomposition_impl(gc_graph *g, int32_t *truss, int32_t *h_kmax
     if (hipStreamSynchronize(s) != hipSuccess) st = GC_EDEVICE;
     if (h_kmax) *h_kmax = k - 1;
   }
-  dfree(own);
   return st;
 }
 
