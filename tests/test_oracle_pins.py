@@ -433,3 +433,23 @@ def test_ktruss_bulk_equals_peel_rmat():
     for k in (3, 4, 6, 9, 15):
         bulk, _ = oracle.ktruss(n, u, v, k, "bulk")
         assert np.array_equal(bulk, oracle.ktruss(n, u, v, k, "peel"))
+
+
+def test_stored_digest_is_reproduced_by_the_oracle():
+    """tests/golden/digests.json holds values written by make_digests.py from
+    the oracle alone: recomputing the R-MAT scale-16 entry (edges, T, support,
+    truss numbers, k-truss masks) gives it back exactly.  Only the oracle's
+    own run time may differ."""
+    import importlib.util
+    import json
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    spec = importlib.util.spec_from_file_location("make_digests",
+                                                  os.path.join(here, "make_digests.py"))
+    md = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(md)
+    name = "rmat_s16_ef16_seed1"
+    rec = md.digest(name)
+    gold = json.load(open(os.path.join(here, "digests.json")))[name]
+    rec.pop("oracle_seconds", None)
+    gold = {k: v for k, v in gold.items() if k != "oracle_seconds"}
+    assert rec == gold
