@@ -574,9 +574,12 @@ def main():
     m = recs[-1][3]
     T = recs[-1][1]
     kmax = recs[-1][2]
-    build_ms = np.mean([r[0][0].elapsed_time(r[0][1]) for r in recs])
-    tc_ms = np.mean([r[0][1].elapsed_time(r[0][2]) for r in recs])
-    dec_ms = np.mean([r[0][2].elapsed_time(r[0][3]) for r in recs])
+    build_steps = [r[0][0].elapsed_time(r[0][1]) for r in recs]
+    tc_steps = [r[0][1].elapsed_time(r[0][2]) for r in recs]
+    dec_steps = [r[0][2].elapsed_time(r[0][3]) for r in recs]
+    build_ms = np.mean(build_steps)
+    tc_ms = np.mean(tc_steps)
+    dec_ms = np.mean(dec_steps)
     ms_per_step = wall * 1000.0 / args.steps
     value = m / (ms_per_step / 1000.0)
 
@@ -615,6 +618,9 @@ def main():
             "triangles": int(T), "kmax": kmax,
         },
         "phases_ms": {"build": build_ms, "triangle_count": tc_ms, "decomposition": dec_ms},
+        # every timed step's phases (HIP events on the step's stream), for the spread
+        "phases_ms_per_step": {"build": build_steps, "triangle_count": tc_steps,
+                               "decomposition": dec_steps},
         "autotune": tuned,
         "decomposition_stats": record_stats or None,
         # the decomposition's dominant kernel (k_peel) is bound by the L1
