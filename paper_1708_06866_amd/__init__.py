@@ -3,7 +3,10 @@ support, k-truss and truss decomposition on an MI355X.
 
 This module only marshals arguments: torch tensors (device memory) become raw
 pointers, the current torch stream becomes the ``hipStream_t``, and status
-codes become exceptions.  Every step of the computation runs in libgc's HIP
+codes become exceptions.  Before any library call it checks what the C ABI
+cannot see: caller-supplied output tensors (dtype, layout, device, length
+where the C call takes no capacity), equal lengths of host pair arrays, and
+ids that fit int32.  Every step of the computation runs in libgc's HIP
 kernels; there is no CPU fallback -- if ``libgc.so`` is missing, or no GPU is
 visible, the calls raise.
 
