@@ -82,8 +82,9 @@ gc_status gc_build_csr(const int32_t *d_src, const int32_t *d_dst,
                        int64_t n_pairs, int32_t n_vertices, uint32_t flags,
                        gc_stream stream, gc_graph **out);
 
-/* Sizes of a handle: vertices, undirected edges m (canonical edge count) and
- * the device bytes the handle currently holds.  Any output pointer may be
+/* Sizes of a handle: vertices, undirected edges m (canonical edge count, the
+ * number of rows of the incidence matrix E of Sec. III-B) and the device
+ * bytes the handle currently holds.  Any output pointer may be
  * NULL. */
 gc_status gc_graph_info(const gc_graph *g, int64_t *n_vertices,
                         int64_t *n_edges, int64_t *device_bytes);
@@ -132,7 +133,10 @@ gc_status gc_ktruss(gc_graph *g, int32_t k, uint8_t *d_in_truss, int64_t cap,
                     gc_stream stream, int64_t *h_m_k);
 
 /* Count strategies per degree bin (the 5 bins split middle vertices by
- * out-degree: <= 32, <= 256, <= 2048, <= 8192, larger):
+ * out-degree: <= 32, <= 256, <= 2048, <= 8192, larger).  A strategy is only
+ * a schedule for the intersections behind the masked product of Alg. 3
+ * (Sec. III-A): it chooses how N+(b) is staged and probed, not what is
+ * counted.
  *   0 linear-probing LDS hash table, load <= 1/2
  *   1 linear-probing LDS hash table, load <= 1/4
  *   2 binary search in the sorted row in HBM (the only one for the last bin)
@@ -176,7 +180,8 @@ gc_status gc_graph_set_strategy(gc_graph *g, const int32_t *h_strategy);
 gc_status gc_truss_decomposition(gc_graph *g, int32_t *d_truss, int64_t cap,
                                  gc_stream stream, int32_t *h_kmax);
 
-/* Counters of the last peeling on this handle (gc_truss_decomposition, or
+/* Counters of the incremental support update (Sec. III-B, Alg. 4's update
+ * of R) in the last peeling on this handle (gc_truss_decomposition, or
  * gc_ktruss with k > 2 unless GC_TRUSS_METHOD=rounds; first `cap` of 41,
  * host): [0] levels that removed edges, [1] rounds, [2] edges removed over
  * all rounds (= m for a decomposition), [3] largest round, [4] compactions,
@@ -190,6 +195,8 @@ gc_status gc_graph_truss_stats(const gc_graph *g, int64_t *h_stats, int32_t cap)
 
 /* ------------------------------------------------------------------------ */
 /* Batches: many independent graphs counted in one launch per degree bin.    */
+/* Not in the paper: a throughput layer; every per-graph result is the one   */
+/* Sec. III defines for that graph alone.                                    */
 /* ------------------------------------------------------------------------ */
 typedef struct gc_batch gc_batch;
 
@@ -252,6 +259,8 @@ void gc_batch_free(gc_batch *b);
 
 /* ------------------------------------------------------------------------ */
 /* Serving: queries on registered graphs with continuous batching.          */
+/* Not in the paper: a serving layer whose queries return the Sec. III-A     */
+/* triangle count or the size of a Sec. III-B k-truss.                       */
 /* ------------------------------------------------------------------------ */
 typedef struct gc_server gc_server;
 
