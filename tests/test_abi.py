@@ -118,6 +118,9 @@ def test_null_handles_rejected_on_the_host(lib):
         f.argtypes = [P]
         f.restype = None
         f(None)
+    lib.gc_batch_graph.argtypes = [P]
+    lib.gc_batch_graph.restype = P
+    assert lib.gc_batch_graph(None) is None
 
 
 @pytest.fixture
