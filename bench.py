@@ -165,7 +165,12 @@ class MemoryWatch:
         return int(self.free0 - self.min_free) if self.min_free is not None else None
 
 
-def algorithmic_bytes(row_ptr: np.ndarray, col: np.ndarray, chunk: int = 128) -> dict:
+# the count kernels' degree bins: middle vertices b by out-degree d+(b)
+COUNT_BIN_LIMITS = (32, 256, 2048, 8192)
+
+
+def algorithmic_bytes(row_ptr: np.ndarray, col: np.ndarray, chunk: int = 128,
+                      bin_limits=COUNT_BIN_LIMITS) -> dict:
     """Bytes a count pass must move with no cache reuse.
 
     B_model_min: the two whole-list schedules (stage the low vertex and stream
@@ -174,7 +179,9 @@ def algorithmic_bytes(row_ptr: np.ndarray, col: np.ndarray, chunk: int = 128) ->
     bytes: what these kernels' schedule moves -- per middle vertex b with
     d+(b) > 0 and an in-edge chunk: the unit (16 B), its two row pointers (8 B)
     and N+(b) staged once per chunk (4 B each); per in-edge a->b: its packed
-    tail range (8 B); per tail element (only x > b can close a triangle): 4 B."""
+    tail range (8 B); per tail element (only x > b can close a triangle): 4 B.
+    bytes_by_bin: the same, split by the degree bin of the middle vertex b
+    (d+(b) <= 32, <= 256, <= 2048, <= 8192, larger): one entry per bin."""
     n = len(row_ptr) - 1
     m = len(col)
     dout = np.diff(row_ptr).astype(np.int64)
@@ -190,11 +197,21 @@ def algorithmic_bytes(row_ptr: np.ndarray, col: np.ndarray, chunk: int = 128) ->
     units = int(chunks.sum())
     staged = int((chunks * dout[has]).sum())
     b = 4 * probes + 8 * in_edges + 4 * staged + 24 * units
+    limits = np.asarray(bin_limits, dtype=np.int64)
+    nb = len(limits) + 1
+    ebin = np.searchsorted(limits, dout[col[live]], side="left")     # bin of each in-edge's b
+    vbin = np.searchsorted(limits, dout[has], side="left")           # bin of each middle vertex
+    probes_b = np.bincount(ebin, weights=tail[live].astype(np.float64), minlength=nb)
+    in_b = np.bincount(ebin, minlength=nb)
+    units_b = np.bincount(vbin, weights=chunks.astype(np.float64), minlength=nb)
+    staged_b = np.bincount(vbin, weights=(chunks * dout[has]).astype(np.float64), minlength=nb)
+    by_bin = [int(4 * round(p_) + 8 * int(i_) + 4 * round(s_) + 24 * round(u_))
+              for p_, i_, s_, u_ in zip(probes_b, in_b, staged_b, units_b)]
     # the two whole-list schedules of the survey's model, for context
     s_src = int((dout.astype(np.int64) ** 2).sum())
     s_dst = int(dout[col].sum())
-    return {"bytes": b, "probes": probes, "in_edges": in_edges, "units": units,
-            "staged": staged, "S_src": s_src, "S_dst": s_dst,
+    return {"bytes": b, "bytes_by_bin": by_bin, "probes": probes, "in_edges": in_edges,
+            "units": units, "staged": staged, "S_src": s_src, "S_dst": s_dst,
             "B_model_min": min(16 * n + 20 * m + 4 * s_dst, 16 * n + 24 * m + 4 * s_src)}
 
 
@@ -654,6 +671,7 @@ def main():
             "algorithmic_model": "B_TC = min(16n+20m+4*S_dst, 16n+24m+4*S_src)",
             "S_src": ab["S_src"], "S_dst": ab["S_dst"],
             "tail_model_bytes": ab["bytes"], "achieved_tail_model": achieved_tail,
+            "tail_model_bytes_by_bin": ab["bytes_by_bin"],
             "frac_tail_model": achieved_tail / HBM_PEAK_GBS, "probes": ab["probes"],
             "pass_ms": tc_ms,
             "achievable_copy_GBps": bw["copy_GBps"],

@@ -30,7 +30,7 @@ def oriented(n, u, v):
     return row_ptr, b.astype(np.int32)
 
 
-def brute(n, row_ptr, col, chunk):
+def brute(n, row_ptr, col, chunk, limits):
     out = {a: list(col[row_ptr[a]:row_ptr[a + 1]]) for a in range(n)}
     dout = {a: len(out[a]) for a in range(n)}
     din = {x: 0 for x in range(n)}
@@ -47,8 +47,20 @@ def brute(n, row_ptr, col, chunk):
     units = sum(-(-din[b] // chunk) for b in range(n) if dout[b] > 0 and din[b] > 0)
     staged = sum(-(-din[b] // chunk) * dout[b] for b in range(n) if dout[b] > 0 and din[b] > 0)
     m = len(col)
+    # the same bytes by the bin of the middle vertex b (limits inclusive)
+    def bin_of(d):
+        return sum(1 for lim in limits if d > lim)
+    by_bin = [0] * (len(limits) + 1)
+    for a in range(n):
+        for i, b in enumerate(out[a]):
+            if dout[b] > 0:
+                by_bin[bin_of(dout[b])] += 8 + 4 * len(out[a][i + 1:])
+    for b in range(n):
+        if dout[b] > 0 and din[b] > 0:
+            c = -(-din[b] // chunk)
+            by_bin[bin_of(dout[b])] += 24 * c + 4 * c * dout[b]
     return {"S_src": s_src, "S_dst": s_dst, "probes": probes, "in_edges": in_edges,
-            "units": units, "staged": staged,
+            "units": units, "staged": staged, "bytes_by_bin": by_bin,
             "B_model_min": min(16 * n + 20 * m + 4 * s_dst, 16 * n + 24 * m + 4 * s_src),
             "bytes": 4 * probes + 8 * in_edges + 4 * staged + 24 * units}
 
@@ -58,10 +70,12 @@ def test_algorithmic_bytes_match_brute_force():
                                  (gg.complete(40), 8), (gg.king(12), 128), (gg.star(50), 16)):
         u, v = oracle.normalise(src, dst, n)
         row_ptr, col = oriented(n, u, v)
-        got = bench.algorithmic_bytes(row_ptr, col, chunk=chunk)
-        want = brute(n, row_ptr, col, chunk)
-        for k, w in want.items():
-            assert got[k] == w, (k, got[k], w)
+        for limits in (bench.COUNT_BIN_LIMITS, (2, 5, 9, 20)):
+            got = bench.algorithmic_bytes(row_ptr, col, chunk=chunk, bin_limits=limits)
+            want = brute(n, row_ptr, col, chunk, limits)
+            for k, w in want.items():
+                assert got[k] == w, (k, got[k], w)
+            assert sum(got["bytes_by_bin"]) == got["bytes"]
 
 
 def test_tail_probes_count_the_wedges_once():
