@@ -77,6 +77,7 @@ def test_tsv_errors(tmp_path, text, status):
     ("%%MatrixMarket matrix array real general\n3 3\n1.0\n", "GC_EINVAL"),           # dense
     ("%%MatrixMarket matrix coordinate complex general\n3 3 1\n1 2 1 1\n", "GC_EINVAL"),
     ("%%MatrixMarket matrix coordinate pattern general\n% no size line\n", "GC_EINVAL"),
+    ("%%MatrixMarket matrix coordinate pattern general\n3000000000 3 0\n", "GC_EOVERFLOW"),
 ])
 def test_mmio_errors(tmp_path, text, status):
     with pytest.raises(gc.GCError) as ei:
@@ -211,3 +212,15 @@ def test_chunked_read_matches_a_plain_parser(tmp_path, seed):
     s2, d2, n2 = gc.gc_read_edges(p)
     assert np.array_equal(s2, s_ref) and np.array_equal(d2, d_ref)
     assert n2 == int(max(s_ref.max(), d_ref.max())) + 1
+
+
+def test_bad_line_in_a_later_chunk_is_named(tmp_path):
+    """A malformed line far into a multi-chunk file fails the read, and the
+    error text quotes that line (not the first chunk's)."""
+    good = "".join("%d\t%d\t1\n" % (i % 1000 + 1, (i * 7) % 1000 + 1) for i in range(200_000))
+    p = write(tmp_path, "late.tsv", good + "17\tbroken-here\t1\n" + good[:5000])
+    assert os.path.getsize(p) > 1 << 20              # above the multi-chunk threshold
+    with pytest.raises(gc.GCError) as ei:
+        gc.gc_read_edges(p)
+    assert ei.value.status == gc.GC_EINVAL
+    assert "17\tbroken-here" in str(ei.value)
