@@ -139,6 +139,8 @@ def ktruss(n: int, u, v, k: int, method: str = "bulk", start=None):
         raise ValueError("k must be >= 2")
     mask = np.ones(max(len(u), 1), np.uint8) if start is None else \
         np.ascontiguousarray(np.asarray(start), dtype=np.uint8).copy()
+    if len(mask) < len(u):
+        raise ValueError("start holds %d entries, %d edges" % (len(mask), len(u)))
     lib = _load()
     if method == "bulk":
         r = lib.oracle_ktruss_bulk(int(n), len(u), _p(u), _p(v), int(k), _p(mask))
