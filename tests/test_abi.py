@@ -239,3 +239,16 @@ def test_header_is_plain_c_and_links(tmp_path):
     assert r.returncode == 0, (r.returncode, r.stdout, r.stderr)
     assert "pairs 3 n 4 first 0-1" in r.stdout
     assert "build -1 GC_EINVAL" in r.stdout and "g=(nil)" in r.stdout
+
+
+def test_every_declaration_is_documented():
+    """Each function of include/gc.h comes right after a comment of its own
+    (meaning, layout, ownership, errors)."""
+    text = open(HEADER).read()
+    undocumented = []
+    for name in declared_functions():
+        decl = re.search(r"^[A-Za-z_][\w \*]*\b%s\s*\(" % name, text, re.M)
+        assert decl is not None, name
+        if not text[:decl.start()].rstrip().endswith("*/"):
+            undocumented.append(name)
+    assert not undocumented, undocumented
