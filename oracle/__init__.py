@@ -17,7 +17,10 @@ Function map (paper passage -> function)
   per-edge support by triangle listing        -> support(method="listing")
   k-truss, Sec. III-B / Alg. 4 (bulk rounds)  -> ktruss(method="bulk")
   k-truss, one-at-a-time peeling              -> ktruss(method="peel")
+  k-truss, peeling by list search (no index)  -> ktruss(method="search")
   truss decomposition, Sec. III-B last para.  -> truss_decomposition
+                                                 (method "bulk", "peel" or
+                                                 "search")
 """
 from __future__ import annotations
 
@@ -66,6 +69,8 @@ def _load():
         lib.oracle_ktruss_bulk.restype = i32
         lib.oracle_ktruss_peel.argtypes = [i32, i64, P, P, i32, P]
         lib.oracle_ktruss_peel.restype = i32
+        lib.oracle_ktruss_search.argtypes = [i32, i64, P, P, i32, P]
+        lib.oracle_ktruss_search.restype = i32
         lib.oracle_truss_decomposition.argtypes = [i32, i64, P, P, i32, P, P]
         lib.oracle_truss_decomposition.restype = ctypes.c_int
         _lib = lib
@@ -146,6 +151,8 @@ def ktruss(n: int, u, v, k: int, method: str = "bulk", start=None):
         r = lib.oracle_ktruss_bulk(int(n), len(u), _p(u), _p(v), int(k), _p(mask))
     elif method == "peel":
         r = lib.oracle_ktruss_peel(int(n), len(u), _p(u), _p(v), int(k), _p(mask))
+    elif method == "search":
+        r = lib.oracle_ktruss_search(int(n), len(u), _p(u), _p(v), int(k), _p(mask))
     else:
         raise ValueError(method)
     if r < 0:
@@ -156,12 +163,15 @@ def ktruss(n: int, u, v, k: int, method: str = "bulk", start=None):
 
 def truss_decomposition(n: int, u, v, method: str = "peel"):
     """``(tau, kmax)``: truss number per canonical edge and the largest k with a
-    non-empty k-truss."""
+    non-empty k-truss.  ``bulk``: Alg. 4's rounds per level; ``peel``:
+    one-at-a-time peeling over a triangle index (3T edge pairs in memory);
+    ``search``: the same peeling with each removed edge's triangles found by
+    searching adjacency lists (memory O(n + m), for the largest graphs)."""
     u, v = _i32(u), _i32(v)
     _check_canonical(u, v, n)
     tau = np.zeros(max(len(u), 1), np.int32)
     kmax = ctypes.c_int32(0)
-    meth = {"bulk": 0, "peel": 1}[method]
+    meth = {"bulk": 0, "peel": 1, "search": 2}[method]
     rc = _load().oracle_truss_decomposition(int(n), len(u), _p(u), _p(v), meth,
                                             _p(tau), ctypes.byref(kmax))
     if rc != 0:

@@ -387,6 +387,121 @@ int32_t oracle_ktruss_peel(int32_t n, int64_t m, const int32_t *u,
 }
 
 /* ------------------------------------------------------------------------- */
+/* Peeling without a triangle index (a third route, for graphs whose index of  */
+/* 3T edge pairs does not fit in memory).  The same one-edge-at-a-time rule as */
+/* peel_edge: on removing edge {a, b}, every triangle {a, b, w} whose edges    */
+/* {a, w} and {b, w} are both still present is destroyed once, and those two   */
+/* edges lose 1.  The triangles are found by intersecting the adjacency lists  */
+/* of a and b directly: the shorter list is walked in increasing order and     */
+/* each neighbour w is binary-searched in the other list, from where the       */
+/* previous search ended (the walked ids only grow).  Entries of removed edges */
+/* stay in a list until they are more than half of it; the list is then        */
+/* rewritten, in order, without them.  Memory is O(n + m).                      */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+  adj_t g;          /* list x occupies g.nbr / g.eid [g.off[x], g.off[x] + len[x]) */
+  int64_t *len;     /* n: entries still stored in list x */
+  int64_t *ndead;   /* n: stored entries of list x whose edge has been removed */
+} live_lists_t;
+
+static void live_lists_free(live_lists_t *L) {
+  adj_free(&L->g); free(L->len); free(L->ndead);
+  L->len = NULL; L->ndead = NULL;
+}
+
+/* list x without the entries of removed edges, order kept */
+static void drop_removed(live_lists_t *L, int32_t x, const uint8_t *alive) {
+  const int64_t b = L->g.off[x], e = b + L->len[x];
+  int64_t w = b;
+  for (int64_t i = b; i < e; ++i)
+    if (alive[L->g.eid[i]]) { L->g.nbr[w] = L->g.nbr[i]; L->g.eid[w] = L->g.eid[i]; ++w; }
+  L->len[x] = w - b;
+  L->ndead[x] = 0;
+}
+
+/* adjacency of the present edges (alive[e] = 1) */
+static int live_lists_build(live_lists_t *L, int32_t n, int64_t m, const int32_t *u,
+                            const int32_t *v, const uint8_t *alive) {
+  L->len = NULL; L->ndead = NULL;
+  if (adj_build(&L->g, n, m, u, v) != 0) return -2;
+  L->len = (int64_t *)malloc(sizeof(int64_t) * ((size_t)n + 1));
+  L->ndead = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+  if (!L->len || !L->ndead) { live_lists_free(L); return -2; }
+  for (int32_t x = 0; x < n; ++x) {
+    L->len[x] = L->g.off[x + 1] - L->g.off[x];
+    drop_removed(L, x, alive);
+  }
+  return 0;
+}
+
+static void lose_one(int32_t *s, int32_t e, int32_t thr, uint8_t *queued, int64_t *queue,
+                     int64_t *qtail) {
+  s[e] -= 1;
+  if (s[e] < thr && !queued[e]) { queued[e] = 1; queue[(*qtail)++] = e; }
+}
+
+static void peel_edge_by_search(live_lists_t *L, const int32_t *u, const int32_t *v,
+                                int64_t e, uint8_t *alive, int32_t *s, int32_t thr,
+                                uint8_t *queued, int64_t *queue, int64_t *qtail) {
+  int32_t a = u[e], b = v[e];
+  alive[e] = 0;
+  if (L->len[a] > L->len[b]) { int32_t t = a; a = b; b = t; }   /* walk the shorter */
+  const int32_t *nbr = L->g.nbr, *eid = L->g.eid;
+  const int64_t ia = L->g.off[a], ea = ia + L->len[a];
+  const int64_t hb = L->g.off[b] + L->len[b];
+  int64_t lb = L->g.off[b];
+  for (int64_t i = ia; i < ea; ++i) {
+    const int32_t eaw = eid[i];
+    if (!alive[eaw]) continue;                    /* {a, w} already removed */
+    const int32_t w = nbr[i];
+    int64_t lo = lb, hi = hb;                     /* first entry of b's list >= w */
+    while (lo < hi) {
+      const int64_t mid = lo + (hi - lo) / 2;
+      if (nbr[mid] < w) lo = mid + 1;
+      else hi = mid;
+    }
+    lb = lo;
+    if (lo == hb || nbr[lo] != w) continue;       /* w is not a neighbour of b */
+    const int32_t ebw = eid[lo];
+    if (!alive[ebw]) continue;                    /* {b, w} removed: destroyed before */
+    lose_one(s, eaw, thr, queued, queue, qtail);
+    lose_one(s, ebw, thr, queued, queue, qtail);
+  }
+  L->ndead[a] += 1;
+  L->ndead[b] += 1;
+  if (2 * L->ndead[a] > L->len[a]) drop_removed(L, a, alive);
+  if (2 * L->ndead[b] > L->len[b]) drop_removed(L, b, alive);
+}
+
+/* k-truss by peeling without a triangle index; in_out as for oracle_ktruss_bulk.
+ * The support of each present edge within the present edges is counted by
+ * the plain definition before peeling starts.  Returns 0 or < 0. */
+int32_t oracle_ktruss_search(int32_t n, int64_t m, const int32_t *u,
+                             const int32_t *v, int32_t k, uint8_t *in_out) {
+  if (k < 2) return -1;
+  adj_t g;
+  if (adj_build(&g, n, m, u, v) != 0) return -2;
+  int32_t *s = (int32_t *)malloc(sizeof(int32_t) * (size_t)(m + 1));
+  uint8_t *queued = (uint8_t *)calloc((size_t)m + 1, 1);
+  int64_t *queue = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m + 1));
+  if (!s || !queued || !queue) { free(s); free(queued); free(queue); adj_free(&g); return -2; }
+  for (int64_t e = 0; e < m; ++e)
+    s[e] = in_out[e] ? common_neighbours(&g, u[e], v[e], in_out) : 0;
+  adj_free(&g);
+  live_lists_t L;
+  if (live_lists_build(&L, n, m, u, v, in_out) != 0) {
+    free(s); free(queued); free(queue); return -2;
+  }
+  int64_t qh = 0, qt = 0;
+  for (int64_t e = 0; e < m; ++e)
+    if (in_out[e] && s[e] < k - 2) { queued[e] = 1; queue[qt++] = e; }
+  while (qh < qt)
+    peel_edge_by_search(&L, u, v, queue[qh++], in_out, s, k - 2, queued, queue, &qt);
+  free(s); free(queued); free(queue); live_lists_free(&L);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Truss decomposition (Sec. III-B, last paragraph): run the k-truss with      */
 /* k = 3 on the whole graph, pass the result on with k + 1, and stop at the    */
 /* first empty result.  tau(e) = the largest k whose k-truss contains e        */
@@ -396,6 +511,9 @@ int32_t oracle_ktruss_peel(int32_t n, int64_t m, const int32_t *u,
 /*   method 0: bulk rounds (oracle_ktruss_bulk) per level, literally chained.  */
 /*   method 1: levelled peeling -- support kept across levels, edges peeled    */
 /*             one at a time with incremental decrements (triangle index).     */
+/*   method 2: the same levels and peeling rule, with each removed edge's      */
+/*             triangles found by searching adjacency lists (no triangle       */
+/*             index; the initial support comes from triangle listing).        */
 /* ------------------------------------------------------------------------- */
 int oracle_truss_decomposition(int32_t n, int64_t m, const int32_t *u,
                                const int32_t *v, int32_t method, int32_t *tau,
@@ -418,18 +536,38 @@ int oracle_truss_decomposition(int32_t n, int64_t m, const int32_t *u,
   } else {
     adj_t g;
     tri_index_t t = {0, NULL, NULL};
-    if (adj_build(&g, n, m, u, v) != 0) { free(alive); return -2; }
-    if (tri_index_build(&g, &t) != 0) { tri_index_free(&t); adj_free(&g); free(alive); return -2; }
-    adj_free(&g);
+    live_lists_t L;
     int32_t *s = (int32_t *)malloc(sizeof(int32_t) * (size_t)(m + 1));
     uint8_t *queued = (uint8_t *)calloc((size_t)m + 1, 1);
     int64_t *queue = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m + 1));
     int64_t *live = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m + 1));
     if (!s || !queued || !queue || !live) {
-      free(s); free(queued); free(queue); free(live); tri_index_free(&t); free(alive);
+      free(s); free(queued); free(queue); free(live); free(alive);
       return -2;
     }
-    present_support(&t, alive, s);
+    if (adj_build(&g, n, m, u, v) != 0) {
+      free(s); free(queued); free(queue); free(live); free(alive);
+      return -2;
+    }
+    if (method == 2) {
+      int64_t *cnt = (int64_t *)calloc((size_t)m + 1, sizeof(int64_t));
+      int64_t T = cnt ? list_triangles(&g, cnt, NULL, NULL) : -2;
+      for (int64_t e = 0; T >= 0 && e < m; ++e) s[e] = (int32_t)cnt[e];
+      free(cnt);
+      adj_free(&g);
+      if (T < 0 || live_lists_build(&L, n, m, u, v, alive) != 0) {
+        free(s); free(queued); free(queue); free(live); free(alive);
+        return -2;
+      }
+    } else {
+      if (tri_index_build(&g, &t) != 0) {
+        tri_index_free(&t); adj_free(&g);
+        free(s); free(queued); free(queue); free(live); free(alive);
+        return -2;
+      }
+      adj_free(&g);
+      present_support(&t, alive, s);
+    }
     int64_t nlive = m;
     for (int64_t e = 0; e < m; ++e) live[e] = e;
     for (;; ++k) {
@@ -438,14 +576,21 @@ int oracle_truss_decomposition(int32_t n, int64_t m, const int32_t *u,
         int64_t e = live[i];
         if (s[e] < k - 2) { queued[e] = 1; queue[qt++] = e; }
       }
-      while (qh < qt) peel_edge(&t, queue[qh++], alive, s, k - 2, queued, queue, &qt);
+      while (qh < qt) {
+        if (method == 2)
+          peel_edge_by_search(&L, u, v, queue[qh++], alive, s, k - 2, queued, queue, &qt);
+        else
+          peel_edge(&t, queue[qh++], alive, s, k - 2, queued, queue, &qt);
+      }
       int64_t w = 0;
       for (int64_t i = 0; i < nlive; ++i)
         if (alive[live[i]]) { tau[live[i]] = k; live[w++] = live[i]; }
       nlive = w;
       if (nlive == 0) break;
     }
-    free(s); free(queued); free(queue); free(live); tri_index_free(&t);
+    free(s); free(queued); free(queue); free(live);
+    if (method == 2) live_lists_free(&L);
+    else tri_index_free(&t);
   }
   *kmax = k - 1;
   free(alive);

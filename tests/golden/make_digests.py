@@ -29,14 +29,15 @@ import oracle  # noqa: E402
 
 OUT = os.path.join(HERE, "digests.json")
 
-# name -> (generator call, decomposition?, ks)
+# name -> (generator call, decomposition route or None, ks)
 WORKLOADS = {
-    "rmat_s16_ef16_seed1": (lambda: gg.rmat(16, 16, seed=1), True, [3, 4, 5, 6]),
-    "rmat_s18_ef16_seed1": (lambda: gg.rmat(18, 16, seed=1), True, [3, 4, 5, 6]),
-    "rmat_s20_ef16_seed1": (lambda: gg.rmat(20, 16, seed=1), True, [3, 4, 5, 6]),
-    "er_n20_m16n_seed2": (lambda: gg.er(1 << 20, 16 << 20, seed=2), True, [3, 4]),
-    "rmat_s24_ef16_seed1": (lambda: gg.rmat(24, 16, seed=1), False, []),
-    "er_n24_m16n_seed2": (lambda: gg.er(1 << 24, 16 << 24, seed=2), False, []),
+    "rmat_s16_ef16_seed1": (lambda: gg.rmat(16, 16, seed=1), "peel", [3, 4, 5, 6]),
+    "rmat_s18_ef16_seed1": (lambda: gg.rmat(18, 16, seed=1), "peel", [3, 4, 5, 6]),
+    "rmat_s20_ef16_seed1": (lambda: gg.rmat(20, 16, seed=1), "peel", [3, 4, 5, 6]),
+    "er_n20_m16n_seed2": (lambda: gg.er(1 << 20, 16 << 20, seed=2), "peel", [3, 4]),
+    "rmat_s22_ef16_seed1": (lambda: gg.rmat(22, 16, seed=1), "search", [3, 4, 5, 6]),
+    "rmat_s24_ef16_seed1": (lambda: gg.rmat(24, 16, seed=1), "search", [3, 4, 5, 6]),
+    "er_n24_m16n_seed2": (lambda: gg.er(1 << 24, 16 << 24, seed=2), "search", [3, 4]),
 }
 
 
@@ -44,7 +45,9 @@ def sha(a: np.ndarray) -> str:
     return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
 
 
-def digest(name: str) -> dict:
+def digest(name: str, stored: dict | None = None) -> dict:
+    """The record of one workload.  With ``stored``, only the decomposition
+    is computed and added to a copy of it."""
     gen, decomp, ks = WORKLOADS[name]
     t0 = time.time()
     src, dst, n = gen()
@@ -52,16 +55,22 @@ def digest(name: str) -> dict:
     del src, dst
     rec = {"n": int(n), "m": int(len(u)), "edges_sha256": sha(np.stack([u, v], 1))}
     print(name, "normalised", len(u), "%.1fs" % (time.time() - t0), flush=True)
-    rec["triangles"] = oracle.triangle_count(n, u, v)
-    print(name, "T", rec["triangles"], "%.1fs" % (time.time() - t0), flush=True)
-    sup = oracle.support(n, u, v, "listing")
-    assert int(sup.astype(np.int64).sum()) == 3 * rec["triangles"]
-    rec["support_sha256"] = sha(sup.astype("<i4"))
-    rec["support_max"] = int(sup.max()) if len(sup) else 0
-    print(name, "support", "%.1fs" % (time.time() - t0), flush=True)
-    del sup
+    if stored is not None:
+        for key in ("n", "m", "edges_sha256"):
+            assert stored[key] == rec[key], (name, key)
+        rec = dict(stored)
+        t0 -= stored.get("oracle_seconds", 0.0)
+    else:
+        rec["triangles"] = oracle.triangle_count(n, u, v)
+        print(name, "T", rec["triangles"], "%.1fs" % (time.time() - t0), flush=True)
+        sup = oracle.support(n, u, v, "listing")
+        assert int(sup.astype(np.int64).sum()) == 3 * rec["triangles"]
+        rec["support_sha256"] = sha(sup.astype("<i4"))
+        rec["support_max"] = int(sup.max()) if len(sup) else 0
+        print(name, "support", "%.1fs" % (time.time() - t0), flush=True)
+        del sup
     if decomp:
-        tau, kmax = oracle.truss_decomposition(n, u, v, "peel")
+        tau, kmax = oracle.truss_decomposition(n, u, v, decomp)
         rec["kmax"] = kmax
         rec["truss_sha256"] = sha(tau.astype("<i4"))
         rec["ktruss"] = {}
@@ -73,16 +82,25 @@ def digest(name: str) -> dict:
     return rec
 
 
-def main(names):
-    data = {}
-    if os.path.exists(OUT):
-        with open(OUT) as f:
-            data = json.load(f)
+def main(args):
+    add_truss = "--add-truss" in args
+    names = [a for a in args if a != "--add-truss"]
     for name in names or list(WORKLOADS):
-        data[name] = digest(name)
-        with open(OUT + ".tmp", "w") as f:
+        rec = None
+        if add_truss:
+            with open(OUT) as f:
+                rec = json.load(f)[name]
+        rec = digest(name, rec)
+        # re-read before writing: several workloads may run side by side
+        data = {}
+        if os.path.exists(OUT):
+            with open(OUT) as f:
+                data = json.load(f)
+        data[name] = rec
+        tmp = "%s.%d.tmp" % (OUT, os.getpid())
+        with open(tmp, "w") as f:
             json.dump(data, f, indent=1, sort_keys=True)
-        os.replace(OUT + ".tmp", OUT)
+        os.replace(tmp, OUT)
 
 
 if __name__ == "__main__":

@@ -43,6 +43,19 @@ MUTANTS = [
      "if (alive[live[i]]) { tau[live[i]] = k + 1; live[w++] = live[i]; }"),
     ("kmax one too high",
      "  *kmax = k - 1;\n", "  *kmax = k;\n"),
+    ("search route restarts past a miss",
+     "    lb = lo;\n", "    lb = lo + 1;\n"),
+    ("search route misses the end of a list",
+     "if (lo == hb || nbr[lo] != w) continue;", "if (lo + 1 >= hb || nbr[lo] != w) continue;"),
+    ("search route: first edge not required present",
+     "    if (!alive[eaw]) continue;                    /* {a, w} already removed */\n", ""),
+    ("search route: second edge not required present",
+     "    if (!alive[ebw]) continue;                    /* {b, w} removed: destroyed before */\n", ""),
+    ("search route misses a decrement",
+     "    lose_one(s, ebw, thr, queued, queue, qtail);\n", ""),
+    ("search route: rewriting a list drops its last entry",
+     "  for (int64_t i = b; i < e; ++i)\n    if (alive[L->g.eid[i]])",
+     "  for (int64_t i = b; i + 1 < e; ++i)\n    if (alive[L->g.eid[i]])"),
 ]
 
 

@@ -189,7 +189,9 @@ def test_exhaustive_five_vertices_ktruss_vs_subset_enumeration():
             want = dense.brute_ktruss(nv, u, v, k)
             bulk, _ = oracle.ktruss(nv, u, v, k, "bulk")
             peel = oracle.ktruss(nv, u, v, k, "peel")
+            search = oracle.ktruss(nv, u, v, k, "search")
             assert np.array_equal(bulk, want) and np.array_equal(peel, want)
+            assert np.array_equal(search, want)
 
 
 def test_five_vertices_decomposition_vs_subset_enumeration():
@@ -197,7 +199,7 @@ def test_five_vertices_decomposition_vs_subset_enumeration():
     until it is empty) against the definition: tau(e) is the largest k whose
     maximal k-truss, enumerated over every edge subset, holds e; kmax is the
     largest tau (0 without edges, reading R2).  160 graphs on 5 vertices and
-    K_5 itself, by both oracle methods."""
+    K_5 itself, by the three oracle methods."""
     nv = 5
     pairs = _all_graphs_on(nv)
     all_u = np.array([p[0] for p in pairs], np.int32)
@@ -213,7 +215,7 @@ def test_five_vertices_decomposition_vs_subset_enumeration():
         want_kmax = int(want.max()) if len(u) else 0
         if sel.all():                                   # K_5: every edge in 3 triangles
             assert want_kmax == 5 and (want == 5).all()
-        for method in ("peel", "bulk"):
+        for method in ("peel", "bulk", "search"):
             tau, kmax = oracle.truss_decomposition(nv, u, v, method)
             assert np.array_equal(tau, want), (int(g), method)
             assert kmax == want_kmax, (int(g), method)
@@ -248,8 +250,10 @@ def test_ktruss_vs_literal_alg4():
             want, want_rounds = dense.ktruss_alg4(n, u, v, k)
             bulk, rounds = oracle.ktruss(n, u, v, k, "bulk")
             peel = oracle.ktruss(n, u, v, k, "peel")
+            search = oracle.ktruss(n, u, v, k, "search")
             assert np.array_equal(bulk, want)
             assert np.array_equal(peel, want)
+            assert np.array_equal(search, want)
             assert rounds == want_rounds
 
 
@@ -259,6 +263,8 @@ def test_truss_certificate_and_nesting_rmat():
     tau, kmax = oracle.truss_decomposition(n, u, v, "peel")
     tau_b, kmax_b = oracle.truss_decomposition(n, u, v, "bulk")
     assert kmax == kmax_b and np.array_equal(tau, tau_b)
+    tau_s, kmax_s = oracle.truss_decomposition(n, u, v, "search")
+    assert kmax == kmax_s and np.array_equal(tau, tau_s)
     sup = oracle.support(n, u, v)
     assert (tau <= sup + 2).all() and (tau >= 2).all()
     prev = np.ones(len(u), bool)
@@ -285,11 +291,40 @@ def test_complete_graph(nk):
     assert T == nk * (nk - 1) * (nk - 2) // 6
     s = oracle.support(n, u, v)
     assert (s == nk - 2).all()
-    tau, kmax = oracle.truss_decomposition(n, u, v)
-    if nk >= 2:
-        assert kmax == nk and (tau == nk).all()      # K_n is an n-truss
-    else:
-        assert kmax == 0
+    for method in ("peel", "bulk", "search"):
+        tau, kmax = oracle.truss_decomposition(n, u, v, method)
+        if nk >= 2:
+            assert kmax == nk and (tau == nk).all()  # K_n is an n-truss
+        else:
+            assert kmax == 0
+
+
+# graph -> kmax of the whole graph in closed form (K_{a,b,c}: min + 2; king
+# graphs: 4; wheels, windmills, books: 3; triangle-free: 2; a disjoint union:
+# the largest of its parts)
+CLOSED_KMAX = [
+    ("tripartite 2,3,5", lambda: gg.complete_tripartite(2, 3, 5), 4),
+    ("tripartite 4,4,6", lambda: gg.complete_tripartite(4, 4, 6), 6),
+    ("king 8", lambda: gg.king(8), 4),
+    ("wheel 9", lambda: gg.wheel(9), 3),
+    ("windmill 7", lambda: gg.windmill(7), 3),
+    ("book 10", lambda: gg.book(10), 3),
+    ("cycle 9", lambda: gg.cycle(9), 2),
+    ("union", lambda: gg.disjoint_union(gg.complete(6), gg.king(4), gg.wheel(7), gg.book(3)), 6),
+]
+
+
+@pytest.mark.parametrize("name,make,kmax", CLOSED_KMAX, ids=[c[0] for c in CLOSED_KMAX])
+def test_closed_form_kmax_every_route(name, make, kmax):
+    """The three decomposition routes reach the closed-form kmax, and the
+    same truss numbers."""
+    n, u, v = canon(*make())
+    taus = []
+    for method in ("peel", "bulk", "search"):
+        tau, km = oracle.truss_decomposition(n, u, v, method)
+        assert km == kmax, (name, method)
+        taus.append(tau)
+    assert np.array_equal(taus[0], taus[1]) and np.array_equal(taus[0], taus[2])
 
 
 @pytest.mark.parametrize("abc", [(1, 1, 1), (1, 2, 3), (2, 2, 2), (2, 3, 5), (4, 4, 6)])
@@ -433,6 +468,7 @@ def test_ktruss_bulk_equals_peel_rmat():
     for k in (3, 4, 6, 9, 15):
         bulk, _ = oracle.ktruss(n, u, v, k, "bulk")
         assert np.array_equal(bulk, oracle.ktruss(n, u, v, k, "peel"))
+        assert np.array_equal(bulk, oracle.ktruss(n, u, v, k, "search"))
 
 
 def test_stored_digest_is_reproduced_by_the_oracle():
