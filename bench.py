@@ -239,21 +239,60 @@ def profiled_traffic(workload: str, scale: int, ef: int, seed: int, strategy) ->
         return None
 
 
-def cpu_baseline(scale: int, ef: int, seed: int) -> dict:
-    """The oracle as it stands, single thread, on R-MAT of `scale` (a bounded
-    sample of the same family): normalise + count + decomposition."""
+def host_cpu() -> dict:
+    """The host's CPU model (/proc/cpuinfo) and the cores this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "cores_available": len(os.sched_getaffinity(0)),
+            "os_cpu_count": os.cpu_count()}
+
+
+def cpu_baseline(scale: int, ef: int, seed: int, all_cores_scale: int) -> dict:
+    """The oracle as it stands, timed on the host's cores, as context.
+
+    value: one thread (the paper's serial mode) on R-MAT of `scale`, a bounded
+    sample of the benchmark's family: normalise + triangle count + truss
+    decomposition.  all_cores: the triangle count on R-MAT of
+    `all_cores_scale` with its outer loop dealt over every core this process
+    may use (per-thread int64 partials; the count equals the serial one),
+    after a serial normalisation."""
     import graphgen as gg
     import oracle
     src, dst, n = gg.rmat(scale, ef, seed=seed)
     t0 = time.perf_counter()
     u, v = oracle.normalise(src, dst, n)
     oracle.triangle_count(n, u, v)
-    oracle.truss_decomposition(n, u, v, "peel")
+    oracle.truss_decomposition(n, u, v, "search")
     dt = time.perf_counter() - t0
-    return {"value": len(u) / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
-            "sample": "R-MAT scale %d ef %d seed %d (m=%d): normalise + triangle count + "
-                      "truss decomposition, %.1f s single-threaded" % (scale, ef, seed, len(u), dt),
-            "seconds": round(dt, 2)}
+    out = {"value": len(u) / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
+           "sample": "R-MAT scale %d ef %d seed %d (m=%d): normalise + triangle count + "
+                     "truss decomposition, %.1f s single-threaded" % (scale, ef, seed, len(u), dt),
+           "seconds": round(dt, 2), "host": host_cpu()}
+    del src, dst, u, v
+    if all_cores_scale > 0:
+        threads = out["host"]["cores_available"]
+        src, dst, n = gg.rmat(all_cores_scale, ef, seed=seed)
+        t0 = time.perf_counter()
+        u, v = oracle.normalise(src, dst, n)
+        t1 = time.perf_counter()
+        T = oracle.triangle_count_threads(n, u, v, threads)
+        t2 = time.perf_counter()
+        out["all_cores"] = {
+            "threads": threads, "workload": "R-MAT scale %d ef %d seed %d" % (
+                all_cores_scale, ef, seed),
+            "m": int(len(u)), "triangles": T, "normalise_s": round(t1 - t0, 2),
+            "count_s": round(t2 - t1, 2), "count_edges_per_s": len(u) / (t2 - t1),
+            "edges_per_s": len(u) / (t2 - t0),
+            "what": "serial normalisation, then the triangle count over %d threads "
+                    "(its adjacency build is serial)" % threads}
+    return out
 
 
 def batch_workload(n_graphs: int, seed: int = 1000, max_scale: int = 16):
@@ -463,6 +502,8 @@ def main():
                     help="edge file (TSV triples or Matrix Market) instead of a generated graph; "
                          "read on the host before timing")
     ap.add_argument("--cpu-scale", type=int, default=18)
+    ap.add_argument("--cpu-all-cores-scale", type=int, default=20,
+                    help="R-MAT scale of the all-cores oracle count (0 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-decomposition", action="store_true",
                     help="step = build + count only")
@@ -689,7 +730,8 @@ def main():
         log("serve: %s" % json.dumps(out["serve"]))
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on R-MAT scale %d ..." % args.cpu_scale)
-        out["cpu_baseline"] = cpu_baseline(args.cpu_scale, args.ef, args.seed)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_scale, args.ef, args.seed,
+                                           args.cpu_all_cores_scale)
     print(json.dumps(out), flush=True)
 
 

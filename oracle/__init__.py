@@ -13,6 +13,7 @@ independent cross-checks on tiny graphs.
 Function map (paper passage -> function)
   normalisation, Sec. II                      -> normalise
   triangle count, Sec. III-A                  -> triangle_count
+  the same count over host threads            -> triangle_count_threads
   per-edge support, Sec. III-B (EA, R == 2)   -> support(method="definition")
   per-edge support by triangle listing        -> support(method="listing")
   k-truss, Sec. III-B / Alg. 4 (bulk rounds)  -> ktruss(method="bulk")
@@ -36,11 +37,12 @@ _lib = None
 
 
 def build(force: bool = True) -> str:
-    """Compile ``liboracle.so`` (plain C, -O2, no OpenMP, no -march)."""
+    """Compile ``liboracle.so`` (plain C, -O2, no OpenMP, no -march; pthreads
+    for the threaded count only)."""
     if force or not os.path.exists(_LIB_PATH):
         src = os.path.join(_HERE, "oracle.c")
         tmp = _LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-o", tmp, src])
+        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-pthread", "-o", tmp, src])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -61,6 +63,8 @@ def _load():
         lib.oracle_normalise.restype = i64
         lib.oracle_triangle_count.argtypes = [i32, i64, P, P]
         lib.oracle_triangle_count.restype = i64
+        lib.oracle_triangle_count_threads.argtypes = [i32, i64, P, P, i32]
+        lib.oracle_triangle_count_threads.restype = i64
         lib.oracle_support.argtypes = [i32, i64, P, P, P]
         lib.oracle_support.restype = ctypes.c_int
         lib.oracle_support_listing.argtypes = [i32, i64, P, P, P]
@@ -119,6 +123,19 @@ def triangle_count(n: int, u, v) -> int:
     t = _load().oracle_triangle_count(int(n), len(u), _p(u), _p(v))
     if t < 0:
         raise MemoryError("oracle_triangle_count failed")
+    return int(t)
+
+
+def triangle_count_threads(n: int, u, v, threads: int) -> int:
+    """The forward-listing count with its outer loop dealt over `threads`
+    host threads (per-thread int64 partials); equal to triangle_count."""
+    u, v = _i32(u), _i32(v)
+    _check_canonical(u, v, n)
+    t = _load().oracle_triangle_count_threads(int(n), len(u), _p(u), _p(v), int(threads))
+    if t == -1:
+        raise ValueError("threads must be in 1..1024")
+    if t < 0:
+        raise MemoryError("oracle_triangle_count_threads failed")
     return int(t)
 
 

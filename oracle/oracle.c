@@ -19,8 +19,12 @@
  *     Every per-edge output (support, truss membership, truss number) is
  *     indexed by that id.
  *   - Counts are int64; supports and truss numbers are int32.
- *   - No parallelism: single thread, as the paper's serial implementations.
+ *   - Single thread, as the paper's serial implementations; the one
+ *     exception is oracle_triangle_count_threads, the same count with the
+ *     outer loop split over threads (for timing the oracle on every host
+ *     core; its result is tested equal to the serial one).
  */
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -172,6 +176,69 @@ int64_t oracle_triangle_count(int32_t n, int64_t m, const int32_t *u,
     }
   }
   free(deg); free(ooff); free(out); adj_free(&g);
+  return T;
+}
+
+/* The same count with the vertices x dealt to `nthreads` threads in turn     */
+/* (x = t, t + nthreads, ...: a static schedule that spreads the high-degree  */
+/* vertices), each thread summing into its own int64 partial.                 */
+typedef struct {
+  const int64_t *ooff;
+  const int32_t *out;
+  int32_t n, t, nthreads;
+  int64_t partial;
+} tc_share_t;
+
+static void *tc_share(void *arg) {
+  tc_share_t *w = (tc_share_t *)arg;
+  int64_t T = 0;
+  for (int32_t x = w->t; x < w->n; x += w->nthreads) {
+    for (int64_t i = w->ooff[x]; i < w->ooff[x + 1]; ++i) {
+      int32_t y = w->out[i];
+      int64_t a = w->ooff[x], ae = w->ooff[x + 1], b = w->ooff[y], be = w->ooff[y + 1];
+      while (a < ae && b < be) {
+        if (w->out[a] < w->out[b]) ++a;
+        else if (w->out[a] > w->out[b]) ++b;
+        else { ++T; ++a; ++b; }
+      }
+    }
+  }
+  w->partial = T;
+  return NULL;
+}
+
+int64_t oracle_triangle_count_threads(int32_t n, int64_t m, const int32_t *u,
+                                      const int32_t *v, int32_t nthreads) {
+  if (nthreads < 1 || nthreads > 1024) return -1;
+  adj_t g;
+  if (adj_build(&g, n, m, u, v) != 0) return -2;
+  int64_t *deg = (int64_t *)malloc(sizeof(int64_t) * ((size_t)n + 1));
+  int64_t *ooff = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+  int32_t *out = (int32_t *)malloc(sizeof(int32_t) * (size_t)(m + 1));
+  tc_share_t *w = (tc_share_t *)calloc((size_t)nthreads, sizeof(tc_share_t));
+  pthread_t *th = (pthread_t *)calloc((size_t)nthreads, sizeof(pthread_t));
+  uint8_t *started = (uint8_t *)calloc((size_t)nthreads, 1);
+  if (!deg || !ooff || !out || !w || !th || !started) {
+    free(deg); free(ooff); free(out); free(w); free(th); free(started); adj_free(&g);
+    return -2;
+  }
+  for (int32_t x = 0; x < n; ++x) deg[x] = g.off[x + 1] - g.off[x];
+  for (int32_t x = 0; x < n; ++x) {
+    ooff[x + 1] = ooff[x];
+    for (int64_t i = g.off[x]; i < g.off[x + 1]; ++i)
+      if (precedes(deg, x, g.nbr[i])) out[ooff[x + 1]++] = g.nbr[i];
+  }
+  int64_t T = 0;
+  for (int32_t t = 0; t < nthreads; ++t) {
+    w[t].ooff = ooff; w[t].out = out; w[t].n = n; w[t].t = t; w[t].nthreads = nthreads;
+    if (pthread_create(&th[t], NULL, tc_share, &w[t]) == 0) started[t] = 1;
+    else tc_share(&w[t]);                        /* no thread: this one does it */
+  }
+  for (int32_t t = 0; t < nthreads; ++t) {
+    if (started[t]) pthread_join(th[t], NULL);
+    T += w[t].partial;
+  }
+  free(deg); free(ooff); free(out); free(w); free(th); free(started); adj_free(&g);
   return T;
 }
 

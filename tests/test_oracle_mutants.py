@@ -53,6 +53,9 @@ MUTANTS = [
      "    if (!alive[ebw]) continue;                    /* {b, w} removed: destroyed before */\n", ""),
     ("search route misses a decrement",
      "    lose_one(s, ebw, thr, queued, queue, qtail);\n", ""),
+    ("threaded count deals vertices with a gap",
+     "for (int32_t x = w->t; x < w->n; x += w->nthreads)",
+     "for (int32_t x = w->t; x < w->n; x += w->nthreads + 1)"),
     ("search route: rewriting a list drops its last entry",
      "  for (int64_t i = b; i < e; ++i)\n    if (alive[L->g.eid[i]])",
      "  for (int64_t i = b; i + 1 < e; ++i)\n    if (alive[L->g.eid[i]])"),
@@ -65,7 +68,7 @@ def run_pins(tmp_path, text):
     lib = os.path.join(tmp_path, "liboracle_mutant.so")
     with open(src, "w") as f:
         f.write(text)
-    subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-o", lib, src])
+    subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-pthread", "-o", lib, src])
     env = dict(os.environ, ORACLE_LIB=lib, PYTHONPATH=ROOT)
     return subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                            os.path.join(ROOT, "tests", "test_oracle_pins.py")],

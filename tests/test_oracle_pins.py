@@ -327,6 +327,22 @@ def test_closed_form_kmax_every_route(name, make, kmax):
     assert np.array_equal(taus[0], taus[1]) and np.array_equal(taus[0], taus[2])
 
 
+@pytest.mark.parametrize("threads", [1, 2, 3, 8])
+def test_threaded_count_equals_closed_forms_and_serial(threads):
+    """The count with its outer loop dealt over threads (the all-cores CPU
+    baseline) gives C(n, 3) on K_n, 4(M-1)^2 on king graphs, 0 without
+    triangles, and the serial count on R-MAT."""
+    for nk in (1, 3, 30):
+        n, u, v = canon(*gg.complete(nk))
+        assert oracle.triangle_count_threads(n, u, v, threads) == nk * (nk - 1) * (nk - 2) // 6
+    n, u, v = canon(*gg.king(16))
+    assert oracle.triangle_count_threads(n, u, v, threads) == 4 * 15 * 15
+    n, u, v = canon(*gg.complete_bipartite(5, 7))
+    assert oracle.triangle_count_threads(n, u, v, threads) == 0
+    n, u, v = canon(*gg.rmat(12, 16, seed=5))
+    assert oracle.triangle_count_threads(n, u, v, threads) == oracle.triangle_count(n, u, v)
+
+
 @pytest.mark.parametrize("abc", [(1, 1, 1), (1, 2, 3), (2, 2, 2), (2, 3, 5), (4, 4, 6)])
 def test_complete_tripartite(abc):
     a, b, c = abc
