@@ -569,7 +569,14 @@ gc_status autotune_bins(const CsrView &c, const UnitStore &u, int *strategy, flo
   if (c.m == 0) return GC_OK;
   hipEvent_t e0, e1;
   GC_HIP(hipEventCreate(&e0));
-  GC_HIP(hipEventCreate(&e1));
+  {
+    const hipError_t e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      set_error(std::string("hipEventCreate: ") + hipGetErrorString(e));
+      return GC_EDEVICE;
+    }
+  }
   gc_status st = GC_OK;
   for (int bin = 0; bin < kCountBins && st == GC_OK; ++bin) {
     if (u.bin_count[bin] == 0) continue;
