@@ -118,6 +118,23 @@ gc_status gc_triangle_count(gc_graph *g, gc_stream stream, int64_t *h_count);
 gc_status gc_edge_support(gc_graph *g, int32_t *d_support, int64_t cap,
                           gc_stream stream);
 
+/* Largest graph (undirected edges) gc_edge_support_noalloc accepts. */
+#define GC_NOALLOC_MAX_EDGES (1 << 24)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * output as gc_edge_support, computed by the same kernels, with no device or
+ * host allocation.  The slot-order counts live in a device array of the
+ * library (4 * GC_NOALLOC_MAX_EDGES bytes = 64 MiB), which each GPU the
+ * library runs on holds until the process ends; the handle's work units are
+ * built by gc_build_csr.  Every call on one GPU shares that array and clears
+ * the part it uses: calls that overlap on one GPU (other streams, other
+ * threads) race and must be serialised by the caller.  m >
+ * GC_NOALLOC_MAX_EDGES or cap < m gives GC_ECAPACITY.  Does not synchronise
+ * `stream`. */
+gc_status gc_edge_support_noalloc(gc_graph *g, int32_t *d_support, int64_t cap,
+                                  gc_stream stream);
+
 /* k-truss (Sec. III-B, Alg. 4): d_in_truss[e] = 1 if canonical edge e belongs
  * to the maximal k-truss, else 0 (device, uint8, m entries).  The result is
  * the fixed point of Alg. 4 (drop every edge with support < k-2 until none

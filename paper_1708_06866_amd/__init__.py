@@ -83,6 +83,7 @@ def lib():
         L.gc_graph_oriented.argtypes = [P, P, P, P, P, i64, i64, P]
         L.gc_triangle_count.argtypes = [P, P, ctypes.POINTER(i64)]
         L.gc_edge_support.argtypes = [P, P, i64, P]
+        L.gc_edge_support_noalloc.argtypes = [P, P, i64, P]
         L.gc_ktruss.argtypes = [P, i32, P, i64, P, ctypes.POINTER(i64)]
         L.gc_truss_decomposition.argtypes = [P, P, i64, P, ctypes.POINTER(i32)]
         L.gc_graph_autotune.argtypes = [P, P, P, P]
@@ -126,7 +127,8 @@ def lib():
                      "gc_server_submit", "gc_server_poll", "gc_server_wait", "gc_server_stats"):
             getattr(L, name).restype = i32
         for name in ("gc_build_csr", "gc_graph_info", "gc_graph_edges", "gc_graph_oriented",
-                     "gc_triangle_count", "gc_edge_support", "gc_ktruss",
+                     "gc_triangle_count", "gc_edge_support", "gc_edge_support_noalloc",
+                     "gc_ktruss",
                      "gc_truss_decomposition", "gc_batch_build", "gc_batch_info",
                      "gc_batch_edge_offsets", "gc_batch_triangle_count",
                      "gc_batch_edge_support", "gc_batch_ktruss", "gc_batch_autotune",
@@ -248,6 +250,9 @@ class Graph:
     def edge_support(self, out=None, stream=None) -> torch.Tensor:
         return gc_edge_support(self, out, stream)
 
+    def edge_support_noalloc(self, out, stream=None) -> torch.Tensor:
+        return gc_edge_support_noalloc(self, out, stream)
+
     def ktruss(self, k: int, out=None, stream=None):
         return gc_ktruss(self, k, out, stream)
 
@@ -339,6 +344,15 @@ def gc_edge_support(g: Graph, out: torch.Tensor | None = None, stream=None) -> t
     _check(lib().gc_edge_support(g.handle, _ptr(out), out.numel(), _stream(stream)),
            "gc_edge_support")
     return out[:m]
+
+
+def gc_edge_support_noalloc(g: Graph, out: torch.Tensor, stream=None) -> torch.Tensor:
+    """gc_edge_support into a caller-supplied int32 tensor, with no allocation
+    by the library (nor here: `out` is required)."""
+    _dev_out(out, torch.int32, 0, "out", g.device)
+    _check(lib().gc_edge_support_noalloc(g.handle, _ptr(out), out.numel(), _stream(stream)),
+           "gc_edge_support_noalloc")
+    return out[:g.m]
 
 
 def gc_ktruss(g: Graph, k: int, out: torch.Tensor | None = None, stream=None):

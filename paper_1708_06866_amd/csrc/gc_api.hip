@@ -1,5 +1,7 @@
 // gc_api.hip -- handle accessors, status text, device memory helpers and the
-// counting entry points gc_triangle_count / gc_edge_support.
+// counting entry points gc_triangle_count / gc_edge_support /
+// gc_edge_support_noalloc.
+#include <mutex>
 #include <new>
 
 #include "gc_graph.h"
@@ -58,6 +60,50 @@ __global__ void k_slot_to_canonical(const int32_t *__restrict__ sup,
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
        i += (int64_t)gridDim.x * blockDim.x)
     out[eid[i]] = sup[i];
+}
+
+static __global__ void k_zero_i32(int32_t *__restrict__ p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+// Slot-order support of gc_edge_support_noalloc: one int32 per oriented edge
+// of the graph being counted.  Every GPU the library runs on holds its own
+// copy until the process ends, and every call on that GPU shares it (calls
+// that overlap on one GPU race).  In host code `scratch` names a host-side
+// stand-in, never the device array: kernels get the address that
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) int32_t scratch[GC_NOALLOC_MAX_EDGES];
+
+constexpr int kScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static int32_t *g_scratch_ptr[kScratchDevices] = {nullptr};
+
+// Device address of `scratch` on device `dev`, which must be current.  The
+// symbol is looked up once per device, on the first call there.
+static gc_status scratch_on_device(int dev, int32_t **out) {
+  if (dev < 0 || dev >= kScratchDevices) {
+    set_error("gc_edge_support_noalloc: device ordinal beyond the library's table");
+    return GC_EDEVICE;
+  }
+  try {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+      void *p = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !p) {
+        set_error(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        return GC_EDEVICE;
+      }
+      g_scratch_ptr[dev] = static_cast<int32_t *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+  } catch (const std::exception &e) {
+    note_host_failure("gc_edge_support_noalloc", e.what());
+    return GC_ENOMEM;
+  }
+  return GC_OK;
 }
 
 }  // namespace gc
@@ -229,6 +275,44 @@ extern "C" gc_status gc_edge_support(gc_graph *g, int32_t *d_support, int64_t ca
     GC_TRY(dalloc(g->t_sup, sizeof(int32_t) * (size_t)m));
     int32_t *sup = static_cast<int32_t *>(g->t_sup.ptr);
     GC_HIP(hipMemsetAsync(sup, 0, sizeof(int32_t) * (size_t)m, s));
+    GC_TRY(slot_support(c, g->units_sup, sup, s));
+    k_slot_to_canonical<<<grid_for(m, 256, 65536), 256, 0, s>>>(sup, c.eid, m, d_support);
+    GC_LAUNCH_CHECK();
+    return GC_OK;
+  });
+}
+
+extern "C" gc_status gc_edge_support_noalloc(gc_graph *g, int32_t *d_support, int64_t cap,
+                                             gc_stream stream) {
+  clear_error();
+  if (!g || (g->m > 0 && !d_support)) {
+    set_error("gc_edge_support_noalloc: invalid argument");
+    return GC_EINVAL;
+  }
+  if (cap < g->m) {
+    set_error("gc_edge_support_noalloc: cap < m");
+    return GC_ECAPACITY;
+  }
+  if (g->m > (int64_t)GC_NOALLOC_MAX_EDGES) {
+    set_error("gc_edge_support_noalloc: m = " + std::to_string(g->m) +
+              " edges exceeds GC_NOALLOC_MAX_EDGES = " + std::to_string(GC_NOALLOC_MAX_EDGES) +
+              "; use gc_edge_support");
+    return GC_ECAPACITY;
+  }
+  if (g->m > 0 && !g->units_sup_ready) {
+    set_error("gc_edge_support_noalloc: the handle has no support work units");
+    return GC_EINVAL;
+  }
+  return on_device(g, [&]() -> gc_status {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (g->m == 0) return GC_OK;
+    const int32_t m = (int32_t)g->m;
+    const CsrView c = g->csr.view(g->n, m);
+    int32_t *sup = nullptr;
+    GC_TRY(scratch_on_device(g->device, &sup));
+    // the previous call's counts are still there: clear the part used
+    k_zero_i32<<<grid_for(m, 256, 65536), 256, 0, s>>>(sup, m);
+    GC_LAUNCH_CHECK();
     GC_TRY(slot_support(c, g->units_sup, sup, s));
     k_slot_to_canonical<<<grid_for(m, 256, 65536), 256, 0, s>>>(sup, c.eid, m, d_support);
     GC_LAUNCH_CHECK();

@@ -334,6 +334,14 @@ extern "C" gc_status gc_build_csr(const int32_t *d_src, const int32_t *d_dst, in
   gc::load_strategy_cache(g->device, g->strategy);
   gc_status st = gc::build_impl(d_src, d_dst, n_pairs, n_vertices, flags,
                                 static_cast<hipStream_t>(stream), g);
+  // The support kernels' work units belong to the handle from the start, so
+  // support (and the allocation-free gc_edge_support_noalloc) needs no
+  // device allocation later.
+  if (st == GC_OK && g->m > 0) {
+    st = gc::build_units_support(g->csr.view(g->n, (int32_t)g->m), g->units_sup, g->ws,
+                                 static_cast<hipStream_t>(stream));
+    if (st == GC_OK) g->units_sup_ready = true;
+  }
   if (st != GC_OK) {
     gc_graph_free(g);
     return st;

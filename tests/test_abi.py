@@ -92,6 +92,7 @@ def test_null_handles_rejected_on_the_host(lib):
         ("gc_graph_edges", [P, P, P, I64, P], [None, None, None, 0, None]),
         ("gc_graph_oriented", [P, P, P, P, P, I64, I64, P], [None] * 5 + [0, 0, None]),
         ("gc_edge_support", [P, P, I64, P], [None, None, 0, None]),
+        ("gc_edge_support_noalloc", [P, P, I64, P], [None, None, 0, None]),
         ("gc_graph_autotune", [P, P, P, P], [None, None, None, None]),
         ("gc_graph_set_strategy", [P, P], [None, None]),
         ("gc_graph_truss_stats", [P, P, I32], [None, None, 0]),
@@ -147,6 +148,7 @@ def test_output_buffers_checked_before_any_library_call(no_library):
     g = NoGraph(ctypes.c_void_p(None), torch.device("cuda", 0))
     cases = (
         (gc.gc_edge_support, torch.int32), (gc.gc_truss_decomposition, torch.int32),
+        (gc.gc_edge_support_noalloc, torch.int32),
         (lambda g_, out: gc.gc_ktruss(g_, 3, out), torch.uint8))
     for call, dtype in cases:
         other = torch.int64 if dtype != torch.int64 else torch.int32
