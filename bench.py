@@ -413,11 +413,19 @@ def serve_pool(n_graphs: int, seed: int = 5000, big_max: int = 18):
 
 
 def bench_serve(gc, n_graphs: int, n_requests: int, big_max: int, budget: int) -> dict:
-    """Poisson arrivals at 0.7 x the one-request-at-a-time capacity; the same
-    trace served with continuous batching and one request at a time.  Half of
-    the requests count triangles, half ask for the 4-truss size."""
+    """Serving at a fixed offered load: Poisson arrivals at 0.7 x the
+    one-request-at-a-time capacity, half triangle counts, half 4-truss sizes,
+    on a pool of R-MAT graphs (scale 10..14 with p = 0.9, else 15..big_max).
+    Every run starts from a fresh server with an empty device cache, so
+    first touches (builds) happen inside the trace, and the HBM budget is
+    below the pool's resident footprint, so graphs are evicted and rebuilt.
+    The same trace is served one request at a time (per call) and with
+    continuous batching; every answer must agree."""
     import threading
+    t = time.perf_counter()
     pool = serve_pool(n_graphs, big_max=big_max)
+    log("serve: generated %d graphs (%d pairs) in %.1fs" % (
+        len(pool), sum(len(g[0]) for g in pool), time.perf_counter() - t))
     rng = np.random.default_rng(7)
     reqs = [(int(rng.integers(0, n_graphs)), int(rng.random() < 0.5)) for _ in range(n_requests)]
 
@@ -425,17 +433,16 @@ def bench_serve(gc, n_graphs: int, n_requests: int, big_max: int, budget: int) -
         srv = gc.Server(budget, mode=mode)
         for s_, d_, n_ in pool:
             srv.add_graph(s_, d_, n_)
-        # first touch of every graph (builds) outside the measurement
-        for t in [srv.submit(i) for i in range(n_graphs)]:
-            srv.wait(t)
         return srv
 
-    def run(srv, trace_gaps):
-        res = [None] * len(reqs)
-        tickets = [None] * len(reqs)
+    def run(mode, trace_gaps, count):
+        srv = make_server(mode)
+        trace = reqs[:count]
+        tickets = [None] * len(trace)
+
         def submitter():
             t_next = time.monotonic()
-            for i, (g, kind) in enumerate(reqs):
+            for i, (g, kind) in enumerate(trace):
                 if trace_gaps is not None:
                     t_next += trace_gaps[i]
                     dt = t_next - time.monotonic()
@@ -446,46 +453,56 @@ def bench_serve(gc, n_graphs: int, n_requests: int, big_max: int, budget: int) -
         t0 = time.monotonic()
         th.start()
         th.join()
-        for i in range(len(reqs)):
-            res[i] = srv.wait(tickets[i])
+        res = [srv.wait(tk) for tk in tickets]
         wall = time.monotonic() - t0
+        stats = srv.stats()
+        srv.close()
         # latency percentiles over the requests after a warm-up tenth
         lat = np.array([r["t_done"] - r["t_submit"] for r in res[len(res) // 10:]])
         edges = sum(r["edges"] for r in res)
-        return res, wall, lat, edges
+        log("serve: mode %d %s: %.1f s, %s" % (mode, "Poisson" if trace_gaps is not None
+                                                else "saturated", wall, stats))
+        return res, wall, lat, edges, stats
 
-    # capacity of the one-at-a-time path: the whole trace submitted at once
-    srv1 = make_server(1)
-    res_sat1, wall_sat1, _, edges = run(srv1, None)
-    cap = len(reqs) / wall_sat1
+    # capacity of the one-at-a-time path: the first quarter of the trace
+    # submitted at once (a cold cache, as the timed runs start)
+    n_sat = max(1, len(reqs) // 4)
+    res_sat1, wall_sat1, _, edges_sat, _ = run(1, None, n_sat)
+    cap = n_sat / wall_sat1
     lam = 0.7 * cap
     gaps = np.random.default_rng(8).exponential(1.0 / lam, len(reqs))
-    res_p1, wall_p1, lat_p1, _ = run(srv1, gaps)
-    srv1.close()
-    srv0 = make_server(0)
-    res_sat0, wall_sat0, _, _ = run(srv0, None)
-    res_p0, wall_p0, lat_p0, _ = run(srv0, gaps)
-    stats0 = srv0.stats()
-    srv0.close()
-    vals = [r["value"] for r in res_sat1]
-    for other in (res_p1, res_sat0, res_p0):
-        assert [r["value"] for r in other] == vals, "results differ between modes"
+    res_p1, wall_p1, lat_p1, edges, stats1 = run(1, gaps, len(reqs))
+    res_p0, wall_p0, lat_p0, _, stats0 = run(0, gaps, len(reqs))
+    res_sat0, wall_sat0, _, _, _ = run(0, None, n_sat)
+    vals = [r["value"] for r in res_p1]
+    assert [r["value"] for r in res_p0] == vals, "results differ between modes"
+    assert [r["value"] for r in res_sat1] == vals[:n_sat] == [r["value"] for r in res_sat0]
+    assert all(r["status"] == 0 for r in res_sat1 + res_p1 + res_sat0 + res_p0)
     pct = lambda a, q: float(np.percentile(a, q) * 1000.0)
+    keep = ("builds", "evictions", "peak_bytes_charged", "deferred")
     return {
         "requests": len(reqs), "graphs": n_graphs, "offered_load_req_per_s": lam,
+        "budget_bytes": budget,
         "per_call": {"p50_ms": pct(lat_p1, 50), "p99_ms": pct(lat_p1, 99),
                      "edges_per_s_at_load": edges / wall_p1,
-                     "saturated_edges_per_s": edges / wall_sat1,
-                     "saturated_req_per_s": len(reqs) / wall_sat1},
+                     "saturated_edges_per_s": edges_sat / wall_sat1,
+                     "saturated_req_per_s": n_sat / wall_sat1,
+                     **{k: stats1[k] for k in keep}},
         "continuous_batching": {"p50_ms": pct(lat_p0, 50), "p99_ms": pct(lat_p0, 99),
                                 "edges_per_s_at_load": edges / wall_p0,
-                                "saturated_edges_per_s": edges / wall_sat0,
-                                "saturated_req_per_s": len(reqs) / wall_sat0,
-                                "max_batch": stats0["max_batch"], "batches": stats0["batches"]},
+                                "saturated_edges_per_s": edges_sat / wall_sat0,
+                                "saturated_req_per_s": n_sat / wall_sat0,
+                                "max_batch": stats0["max_batch"], "batches": stats0["batches"],
+                                "truss_batches": stats0["truss_batches"],
+                                "max_truss_batch": stats0["max_truss_batch"],
+                                **{k: stats0[k] for k in keep}},
         "exact_agreement": True,
         "workload": "R-MAT ef 16 pool, scale 10..14 (p=0.9) / 15..%d; 50%% triangle count, "
-                    "50%% 4-truss size; Poisson arrivals at 0.7 x per-call capacity; "
-                    "latency percentiles over the requests after the first tenth" % big_max,
+                    "50%% 4-truss size; Poisson arrivals at 0.7 x per-call capacity (saturated "
+                    "rates over the first quarter of the trace submitted at once); every run "
+                    "from an empty device cache (first touches inside the trace) under a "
+                    "%.0f GiB budget; latency percentiles over the requests after the first "
+                    "tenth" % (big_max, budget / (1 << 30)),
     }
 
 
@@ -512,10 +529,12 @@ def main():
     ap.add_argument("--batch-graphs", type=int, default=4096,
                     help="graphs in the batched-path comparison (0: skip)")
     ap.add_argument("--batch-max-scale", type=int, default=16)
-    ap.add_argument("--serve-requests", type=int, default=5000,
+    ap.add_argument("--serve-requests", type=int, default=20000,
                     help="requests in the serving comparison (0: skip)")
-    ap.add_argument("--serve-graphs", type=int, default=512)
-    ap.add_argument("--serve-big-max", type=int, default=20)
+    ap.add_argument("--serve-graphs", type=int, default=1024)
+    ap.add_argument("--serve-big-max", type=int, default=22)
+    ap.add_argument("--serve-budget-gib", type=float, default=64.0,
+                    help="HBM budget of the server (below the pool's resident footprint)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one elementwise int32 kernel over 1 GiB (reads 1 GiB, "
                          "writes 1 GiB) so HBM counters can be scaled against known bytes")
@@ -726,7 +745,7 @@ def main():
     if args.serve_requests > 0:
         log("serving: %d requests on %d graphs ..." % (args.serve_requests, args.serve_graphs))
         out["serve"] = bench_serve(gc, args.serve_graphs, args.serve_requests,
-                                   args.serve_big_max, 64 << 30)
+                                   args.serve_big_max, int(args.serve_budget_gib * (1 << 30)))
         log("serve: %s" % json.dumps(out["serve"]))
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on R-MAT scale %d ..." % args.cpu_scale)

@@ -308,18 +308,24 @@ typedef struct {
 /* Start a server on the current device with an HBM budget in bytes.  A
  * scheduler thread keeps built graphs resident (evicting idle ones, least
  * recently used first, when the budget needs room), admits a request only
- * when the budget can hold its graph's build, and runs every triangle-count
- * request whose graph is resident in one batched launch per degree bin,
- * forming the next batch from whatever arrived while the previous one ran.
- * k-truss queries run on a worker thread with their own stream. */
+ * when the budget can hold its graph's build (builds run on a thread and
+ * stream of their own), and runs every triangle-count request whose graph is
+ * resident in one batched launch per degree bin, forming the next batch from
+ * whatever arrived while the previous one ran.  A worker thread runs every
+ * queued k-truss query with the same k as one batch: the graphs' CSRs are
+ * concatenated on the device into their disjoint union, which is peeled
+ * once; each graph's k-truss is its slice of the union's.  The union and its
+ * peeling state are charged to the budget while the batch runs. */
 gc_status gc_server_create(int64_t budget_bytes, gc_server **out);
 
 /* 0 = continuous batching (default); 1 = one request at a time in arrival
- * order with the same cache (the per-call comparison). */
+ * order with the same cache, each k-truss by gc_ktruss on its graph's own
+ * handle (the per-call comparison). */
 gc_status gc_server_set_mode(gc_server *s, int32_t mode);
 
 /* Register a graph: raw pairs in host memory (copied), ids in
- * [0, n_vertices).  GC_ENOMEM if its build can never fit the budget. */
+ * [0, n_vertices).  GC_ENOMEM if its build and a k-truss batch of it alone
+ * cannot fit the budget together. */
 gc_status gc_server_add_graph(gc_server *s, const int32_t *h_src,
                               const int32_t *h_dst, int64_t n_pairs,
                               int32_t n_vertices, int32_t *graph_id);
@@ -333,9 +339,9 @@ gc_status gc_server_poll(gc_server *s, int64_t ticket, gc_result *out);
 /* Block until the query completes, then as gc_server_poll. */
 gc_status gc_server_wait(gc_server *s, int64_t ticket, gc_result *out);
 
-/* h_stats[10]: completed, batches, largest batch, builds, evictions, bytes
- * charged now, peak bytes charged, admissions deferred for memory, resident
- * graphs, budget. */
+/* h_stats[12]: completed, count batches, largest count batch, builds,
+ * evictions, bytes charged now, peak bytes charged, admissions deferred for
+ * memory, resident graphs, budget, k-truss batches, largest k-truss batch. */
 gc_status gc_server_stats(gc_server *s, int64_t *h_stats);
 
 /* Stop the threads and release every resident graph (NULL is a no-op). */

@@ -546,7 +546,8 @@ class Server:
     """A gc_server: registered graphs, queries with continuous batching."""
 
     STAT_NAMES = ("completed", "batches", "max_batch", "builds", "evictions", "bytes_charged",
-                  "peak_bytes_charged", "deferred", "resident_graphs", "budget")
+                  "peak_bytes_charged", "deferred", "resident_graphs", "budget",
+                  "truss_batches", "max_truss_batch")
 
     def __init__(self, budget_bytes: int, mode: int = 0):
         torch.cuda.current_device()  # make sure the HIP runtime is up on this device
@@ -613,7 +614,7 @@ class Server:
         return self._res(r)
 
     def stats(self) -> dict:
-        v = _np.zeros(10, dtype=_np.int64)
+        v = _np.zeros(len(self.STAT_NAMES), dtype=_np.int64)
         _check(lib().gc_server_stats(self.handle, ctypes.c_void_p(v.ctypes.data)),
                "gc_server_stats")
         return dict(zip(self.STAT_NAMES, (int(x) for x in v)))

@@ -21,26 +21,43 @@ void note_host_failure(const char *where, const char *what) noexcept {
   }
 }
 
+static thread_local hipStream_t t_alloc_stream = nullptr;  // AllocScope
+static thread_local hipStream_t t_free_stream = nullptr;   // FreeScope
+
+AllocScope::AllocScope(hipStream_t s) : prev(t_alloc_stream) { t_alloc_stream = s; }
+AllocScope::~AllocScope() { t_alloc_stream = prev; }
+FreeScope::FreeScope(hipStream_t s) : prev(t_free_stream) { t_free_stream = s; }
+FreeScope::~FreeScope() { t_free_stream = prev; }
+
 gc_status dalloc(DeviceBuffer &b, size_t bytes) {
   if (bytes == 0) bytes = 256;
   if (b.ptr && b.bytes >= bytes) return GC_OK;
   dfree(b);
-  hipError_t e = hipMalloc(&b.ptr, bytes);
+  const bool ordered = t_alloc_stream != nullptr;
+  hipError_t e = ordered ? hipMallocAsync(&b.ptr, bytes, t_alloc_stream) : hipMalloc(&b.ptr, bytes);
   if (e != hipSuccess) {
     b.ptr = nullptr;
     b.bytes = 0;
     (void)hipGetLastError();
-    set_error(std::string("hipMalloc(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
+    set_error(std::string(ordered ? "hipMallocAsync(" : "hipMalloc(") + std::to_string(bytes) +
+              "): " + hipGetErrorString(e));
     return e == hipErrorOutOfMemory ? GC_ENOMEM : GC_EDEVICE;
   }
   b.bytes = bytes;
+  b.ordered = ordered;
+  b.ord = t_alloc_stream;
   return GC_OK;
 }
 
 void dfree(DeviceBuffer &b) {
-  if (b.ptr) (void)hipFree(b.ptr);
+  if (b.ptr) {
+    if (b.ordered) (void)hipFreeAsync(b.ptr, t_free_stream ? t_free_stream : b.ord);
+    else (void)hipFree(b.ptr);
+  }
   b.ptr = nullptr;
   b.bytes = 0;
+  b.ord = nullptr;
+  b.ordered = false;
 }
 
 // Run `fn` with the handle's device current, restoring the caller's device.

@@ -63,10 +63,42 @@ inline gc_status guard_host(const char *where, F &&body) noexcept {
 struct DeviceBuffer {
   void *ptr = nullptr;
   size_t bytes = 0;
+  hipStream_t ord = nullptr;  // stream-ordered allocation: released on this stream
+  bool ordered = false;
 };
 
 gc_status dalloc(DeviceBuffer &b, size_t bytes);  // (re)allocates if too small
 void dfree(DeviceBuffer &b);
+
+// Stream-ordered device memory for the calling thread.  hipFree waits for
+// the whole device, and while it waits other threads' launches stall too.
+// While an AllocScope is alive, dalloc takes memory with hipMallocAsync on
+// the scope's stream, and such a buffer is later released with hipFreeAsync:
+// on the stream it was allocated on, or on the stream of a FreeScope alive
+// at the time of release (for buffers that no work in flight uses any more).
+// Neither waits for work on other streams.  Outside any scope dalloc / dfree
+// use hipMalloc / hipFree.  The streams must outlive the buffers.
+struct AllocScope {
+  hipStream_t prev;
+  explicit AllocScope(hipStream_t s);
+  ~AllocScope();
+};
+struct FreeScope {
+  hipStream_t prev;
+  explicit FreeScope(hipStream_t s);
+  ~FreeScope();
+};
+
+// Device memory an allocation holds: the HIP allocator rounds buffers above
+// 2 MiB up to 2 MiB multiples, and smaller ones up to 4 KiB pages plus a
+// header (measured on MI355X: 256 B takes 10.2 KiB, 64 KiB takes 71.7 KiB,
+// 1 MiB takes 1 MiB, 3 MiB takes 4 MiB).
+inline size_t held_bytes(const DeviceBuffer &b) {
+  if (!b.ptr) return 0;
+  constexpr size_t kBig = size_t(2) << 20, kPage = 4096, kHeader = 8192;
+  return b.bytes > kBig ? (b.bytes + kBig - 1) / kBig * kBig
+                        : (b.bytes + kPage - 1) / kPage * kPage + kHeader;
+}
 
 // Carves 256-byte aligned sub-buffers out of one allocation.  reserve() grows
 // the backing allocation (only between calls; contents are not preserved).

@@ -82,10 +82,27 @@ struct gc_graph {
   // floor(log2(frontier size)), [37] candidates examined, [38] searched,
   // [39] triangles found, [40] triangles destroyed (subtracted)
   int64_t peel_stats[41] = {0};
+  template <class F>
+  void each_buffer(F &&f) const {
+    for (const gc::DeviceBuffer *b : {&u, &v, &rank, &vid, &units.units, &units_sup.units, &ws.buf,
+                                      &work_units.units, &t_sup, &t_flag, &t_pos, &t_misc})
+      f(*b);
+    for (const gc::CsrStore *c : {&csr, &work[0], &work[1]})
+      for (const gc::DeviceBuffer *b : {&c->row_ptr, &c->col, &c->src, &c->eid, &c->in_ptr,
+                                        &c->in_tail, &c->in_edge})
+        f(*b);
+  }
+  // bytes requested from the allocator
   size_t device_bytes() const {
-    return u.bytes + v.bytes + rank.bytes + vid.bytes + csr.bytes() + units.units.bytes +
-           units_sup.units.bytes + ws.buf.bytes + work[0].bytes() + work[1].bytes() +
-           work_units.units.bytes + t_sup.bytes + t_flag.bytes + t_pos.bytes + t_misc.bytes;
+    size_t t = 0;
+    each_buffer([&](const gc::DeviceBuffer &b) { t += b.bytes; });
+    return t;
+  }
+  // bytes the allocator holds for them (its rounding included)
+  size_t device_bytes_held() const {
+    size_t t = 0;
+    each_buffer([&](const gc::DeviceBuffer &b) { t += gc::held_bytes(b); });
+    return t;
   }
   void release() {
     gc::dfree(u); gc::dfree(v); gc::dfree(rank); gc::dfree(vid);
