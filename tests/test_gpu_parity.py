@@ -291,8 +291,9 @@ DIGEST_GENS = {
     "rmat_s18_ef16_seed1": lambda: gg.rmat(18, 16, seed=1),
     "rmat_s20_ef16_seed1": lambda: gg.rmat(20, 16, seed=1),
     "er_n20_m16n_seed2": lambda: gg.er(1 << 20, 16 << 20, seed=2),
-    # the full-size workloads (decomposition digests only up to scale 20;
-    # the scale-24 decomposition is checked by properties below)
+    "rmat_s22_ef16_seed1": lambda: gg.rmat(22, 16, seed=1),
+    # the full-size workloads: their truss numbers come from the oracle's
+    # index-free peeling route (the triangle index does not fit in memory)
     "rmat_s24_ef16_seed1": lambda: _rmat24(),
     "er_n24_m16n_seed2": lambda: gg.er(1 << 24, 16 << 24, seed=2),
 }
@@ -332,8 +333,8 @@ def test_against_oracle_digest(name):
 
 
 def test_scale24_decomposition_properties():
-    """Full decomposition of the scale-24 R-MAT graph (too large for the
-    oracle's decomposition): every triangle is destroyed exactly once and every
+    """Full decomposition of the scale-24 R-MAT graph, checked by properties
+    beside the oracle's digest: every triangle is destroyed exactly once and every
     edge removed once; no truss number exceeds support + 2; and the top level
     (edges with truss number kmax) is a kmax-truss whose minimum support, counted
     here by the masked product (A A) .* A on that subgraph, is exactly kmax - 2
