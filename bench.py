@@ -9,13 +9,18 @@ value = m / step time, m = undirected edges after normalisation (the rate of
 Sec. IV-B: edges over execution time, file reading excluded).
 
 Also reported (one JSON line, rank 0):
-  roofline      the triangle-count pass against HBM peak: algorithmic bytes
-                B_TC = min(16n+20m+4 S_dst, 16n+24m+4 S_src) per pass / measured
-                pass time (HIP events on the stream the kernels run on), with
-                the counter-measured HBM bytes of the pass beside it;
-  cpu_baseline  the CPU oracle timed on a bounded sample (a smaller R-MAT of
-                the same family), single thread;
-  phases        build / count / decomposition times.
+  roofline      the dominant triangle-count kernel (the longest degree-bin
+                launch) against HBM peak: its own algorithmic bytes (the
+                tail model of the schedule) / its kernel time (HIP events around
+                the launch on the stream it runs on), with its counter-measured
+                HBM bytes per launch beside it; the whole pass, and the
+                whole-list model B_TC = min(16n+20m+4 S_dst, 16n+24m+4 S_src)
+                as context;
+  cpu_baseline  the CPU oracle timed on the host: one thread on a bounded
+                sample (a smaller R-MAT of the same family), and the count
+                over every host core at R-MAT scale 20, with the CPU model;
+  phases        build / count / decomposition times;
+  batch, serve  the batched and serving paths against one graph per call.
 
 Usage: python bench.py [--steps K] [--warmup W] [--scale 24] [--workload rmat|er]
 """
@@ -167,6 +172,7 @@ class MemoryWatch:
 
 # the count kernels' degree bins: middle vertices b by out-degree d+(b)
 COUNT_BIN_LIMITS = (32, 256, 2048, 8192)
+COUNT_BIN_NAMES = ("d+ <= 32", "d+ 33..256", "d+ 257..2048", "d+ 2049..8192", "d+ > 8192")
 
 
 def algorithmic_bytes(row_ptr: np.ndarray, col: np.ndarray, chunk: int = 128,
@@ -215,26 +221,42 @@ def algorithmic_bytes(row_ptr: np.ndarray, col: np.ndarray, chunk: int = 128,
             "B_model_min": min(16 * n + 20 * m + 4 * s_dst, 16 * n + 24 * m + 4 * s_src)}
 
 
-def profiled_traffic(workload: str, scale: int, ef: int, seed: int, strategy) -> int | None:
-    """HBM bytes per count pass from the committed rocprofv3 counter summary
-    (FETCH_SIZE + WRITE_SIZE, each scaled by a 1 GiB elementwise kernel), if
-    that summary was taken on this workload, with these strategies and with
-    the count kernels' current source; else None."""
+def count_kernel_name(b: int, strategy: int) -> str:
+    """Kernel that runs degree bin b of the count with a given strategy (the
+    strategy numbers of include/gc.h)."""
+    if strategy == 2 or b == 4:
+        return "gc::k_tc_search"
+    if strategy == 5:
+        return "gc::k_tc_group<6, 16>" if b == 0 else "gc::k_tc_group<9, 64>"
+    if strategy in (0, 1):
+        return "gc::k_tc_lds<gc::LinTable<%d> >" % ((6, 9, 12, 14)[b] + strategy)
+    return "gc::k_tc_lds<gc::BucketTable<%d> >" % ((4, 7, 10, 12)[b] + (strategy == 4))
+
+
+def profiled_traffic(kernel: str, workload: str, scale: int, ef: int, seed: int, strategy):
+    """HBM bytes of one launch of `kernel` from the committed rocprofv3
+    counter summary (FETCH_SIZE + WRITE_SIZE, each scaled by a plain
+    elementwise kernel of known size), if that summary was taken on this
+    workload with these strategies and the count kernels' current source;
+    else None (the kernel changed since the counters were taken)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "tc_count_rmat_s24.md")
     src = os.path.join(ROOT, "paper_1708_06866_amd", "csrc", "gc_count.hip")
     if not (os.path.exists(path) and os.path.exists(src)) or strategy is None:
         return None
-    kv = {}
+    kv, traffic = {}, {}
     for line in open(path):
-        if ":" in line and not line.startswith(("#", "|", " ")):
+        if line.startswith("traffic_bytes_per_launch "):
+            name, val = line[len("traffic_bytes_per_launch "):].rsplit("=", 1)
+            traffic[name.strip()] = int(val)
+        elif ":" in line and not line.startswith(("#", "|", " ")):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
     try:
         ok = (kv["count_source_sha256"] == hashlib.sha256(open(src, "rb").read()).hexdigest()
               and kv["workload"] == "%s %d %d %d" % (workload, scale, ef, seed)
               and [int(x) for x in kv["strategy"].split()] == list(strategy))
-        return int(kv["traffic_bytes_per_pass"]) if ok else None
+        return traffic.get(kernel) if ok else None
     except (KeyError, ValueError):
         return None
 
@@ -579,6 +601,7 @@ def main():
     stream = torch.cuda.current_stream()
     tau_buf = None
     record_stats = {}
+    count_ms_steps = []   # per step: kernel ms of each degree bin's count launch
 
     tuned = None
     if not args.no_autotune:
@@ -601,6 +624,7 @@ def main():
         ev[1].record(stream)
         T = g.triangle_count()
         ev[2].record(stream)
+        count_ms_steps.append(g.count_times())
         kmax = None
         if not args.no_decomposition:
             if tau_buf is None or tau_buf.numel() < g.m:
@@ -630,6 +654,7 @@ def main():
     torch.cuda.synchronize()
 
     recs = []
+    count_ms_steps.clear()
     torch.cuda.synchronize()
     energy = EnergyMeter(torch, dev)
     memory = MemoryWatch(torch, dev)
@@ -660,16 +685,27 @@ def main():
     ms_per_step = wall * 1000.0 / args.steps
     value = m / (ms_per_step / 1000.0)
 
-    # algorithmic bytes of the count pass: the per-unit model of the
-    # measurement plan, B_TC = min(16n + 20m + 4 S_dst, 16n + 24m + 4 S_src)
-    # (every list element of the streamed side read once per work unit); the
-    # kernels stream only the tail of each list past the staged vertex, so
-    # they move fewer bytes than B_TC -- that tighter count is reported beside
-    tc_bytes = ab["B_model_min"]
-    achieved = tc_bytes / (tc_ms / 1000.0) / 1e9
+    # The count pass against the HBM roofline.  Its dominant kernel (the
+    # launch of the degree bin that takes longest) is measured on its own
+    # algorithmic bytes: the schedule's tail model (4 B per tail element
+    # streamed, 8 B per in-edge, 4 B per staged element per unit, 24 B per
+    # unit) over the bin's kernel time from HIP events around that launch on
+    # the stream it runs on, averaged over the timed steps.  The whole pass is
+    # given beside it, and so is B_TC = min(16n + 20m + 4 S_dst, 16n + 24m +
+    # 4 S_src), the whole-list model of Alg. 3 (every element of the streamed
+    # lists read per unit): the kernels stream only the tails, so B_TC
+    # overstates the bytes they move.
+    bin_ms = np.mean(np.array(count_ms_steps, dtype=np.float64), axis=0)
+    dom = int(np.argmax(bin_ms))
+    strategy = tuned["strategy"] if tuned else None
+    dom_kernel = count_kernel_name(dom, strategy[dom] if strategy else (2 if dom == 4 else 0))
+    dom_bytes = ab["bytes_by_bin"][dom]
+    achieved = dom_bytes / (bin_ms[dom] / 1000.0) / 1e9
+    pass_ms = float(bin_ms.sum())
     bw = stream_bandwidth(torch, dev)
     log("achievable bandwidth: copy %.0f GB/s (read + write)" % bw["copy_GBps"])
-    achieved_tail = ab["bytes"] / (tc_ms / 1000.0) / 1e9
+    traffic = None if args.input else profiled_traffic(
+        dom_kernel, args.workload, args.scale, args.ef, args.seed, strategy)
     out = {
         "metric": "triangle-count and k-truss edges/sec at R-MAT scale 24",
         "value": value,
@@ -706,6 +742,18 @@ def main():
         # decomposition phase
         "peel_candidates_per_s": (record_stats["candidates"] / (dec_ms / 1000.0)
                                   if record_stats and dec_ms > 0 else None),
+        # the decomposition's bytes by a per-candidate model: each candidate
+        # reads its list entry (4 B) and its edge's state (1 B); each search
+        # ends on one 4-byte key; each destroyed triangle updates two
+        # supports (4-byte read-modify-write each); over the phase time
+        "peel_model": (lambda mb: {
+            "model_bytes": mb, "GBps": mb / (dec_ms / 1000.0) / 1e9,
+            "frac": mb / (dec_ms / 1000.0) / 1e9 / HBM_PEAK_GBS,
+            "model": "5 B per candidate + 4 B per search + 16 B per destroyed triangle",
+            "note": "the peel is bound by the L1 misses a CU keeps in flight (binary "
+                    "searches), not by these bytes"})(
+            5 * record_stats["candidates"] + 4 * record_stats["searches"]
+            + 16 * record_stats["triangles_destroyed"]) if record_stats and dec_ms > 0 else None,
         "tc_edges_per_s": m / (tc_ms / 1000.0),
         # Sec. IV metrics beside the rate: energy of the timed steps from the
         # GPU's energy counter, rate per watt, and device memory
@@ -720,20 +768,27 @@ def main():
         "input_read_s": read_s,
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None if args.input else profiled_traffic(
-                args.workload, args.scale, args.ef, args.seed,
-                tuned["strategy"] if tuned else None),
-            "kernel": "triangle-count pass (k_tc_lds / k_tc_search, one dispatch per degree bin)",
-            "traffic_source": "profiles/tc_count_rmat_s24.md (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
-                              "calibrated; null unless taken on these kernels and strategies)",
-            "algorithmic_bytes": tc_bytes,
-            "algorithmic_model": "B_TC = min(16n+20m+4*S_dst, 16n+24m+4*S_src)",
-            "S_src": ab["S_src"], "S_dst": ab["S_dst"],
-            "tail_model_bytes": ab["bytes"], "achieved_tail_model": achieved_tail,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": "%s: triangle count, degree bin %d (%s)" % (
+                dom_kernel, dom, COUNT_BIN_NAMES[dom]),
+            "kernel_ms": float(bin_ms[dom]),
+            "algorithmic_bytes": dom_bytes,
+            "algorithmic_model": "per launch: 4 B per tail element streamed + 8 B per in-edge "
+                                 "+ 4 B per staged element per unit + 24 B per unit, over the "
+                                 "bin's units",
+            "traffic_source": "profiles/tc_count_rmat_s24.md (rocprofv3 FETCH_SIZE + WRITE_SIZE "
+                              "per launch, calibrated on an elementwise kernel; null unless "
+                              "taken on the current count source with these strategies)",
+            "count_ms_by_bin": [float(x) for x in bin_ms],
             "tail_model_bytes_by_bin": ab["bytes_by_bin"],
-            "frac_tail_model": achieved_tail / HBM_PEAK_GBS, "probes": ab["probes"],
-            "pass_ms": tc_ms,
+            "pass": {"kernel_ms": pass_ms, "tail_model_bytes": ab["bytes"],
+                     "achieved": ab["bytes"] / (pass_ms / 1000.0) / 1e9,
+                     "frac": ab["bytes"] / (pass_ms / 1000.0) / 1e9 / HBM_PEAK_GBS,
+                     "B_TC": ab["B_model_min"], "S_src": ab["S_src"], "S_dst": ab["S_dst"],
+                     "B_TC_per_s_GBps": ab["B_model_min"] / (pass_ms / 1000.0) / 1e9,
+                     "B_TC_note": "whole-list model of Alg. 3, context only: the kernels "
+                                  "stream only list tails, so B_TC / t overstates moved bytes",
+                     "probes": ab["probes"]},
             "achievable_copy_GBps": bw["copy_GBps"],
             "frac_of_achievable_copy": achieved / bw["copy_GBps"],
         },

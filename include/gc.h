@@ -175,6 +175,13 @@ gc_status gc_ktruss(gc_graph *g, int32_t k, uint8_t *d_in_truss, int64_t cap,
 gc_status gc_graph_autotune(gc_graph *g, gc_stream stream, int32_t *h_strategy,
                             float *h_ms);
 
+/* Kernel time of each degree bin's count launch in the last
+ * gc_triangle_count on this handle: h_ms[b] (host, first `cap` of 5) in
+ * milliseconds, from HIP events recorded around each launch on the call's
+ * stream (0 for an empty bin, -1 before any count).  For the measurement of
+ * the count against the HBM roofline (Sec. IV-B's rate, per kernel). */
+gc_status gc_graph_count_times(const gc_graph *g, float *h_ms, int32_t cap);
+
 /* Set the 5 per-bin strategies (GC_EINVAL if one is not admissible). */
 gc_status gc_graph_set_strategy(gc_graph *g, const int32_t *h_strategy);
 

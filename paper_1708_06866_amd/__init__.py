@@ -92,6 +92,8 @@ def lib():
         L.gc_graph_set_strategy.restype = i32
         L.gc_graph_truss_stats.argtypes = [P, P, i32]
         L.gc_graph_truss_stats.restype = i32
+        L.gc_graph_count_times.argtypes = [P, P, i32]
+        L.gc_graph_count_times.restype = i32
         L.gc_graph_free.argtypes = [P]
         L.gc_graph_free.restype = None
         L.gc_status_str.argtypes = [i32]
@@ -268,6 +270,15 @@ class Graph:
                                        ctypes.c_void_p(st.ctypes.data),
                                        ctypes.c_void_p(ms.ctypes.data)), "gc_graph_autotune")
         return st, ms.reshape(N_BINS, N_STRATEGIES)
+
+    def count_times(self):
+        """Kernel time (ms) of each degree bin's count launch in the last
+        triangle_count() on this handle (HIP events; -1 before one)."""
+        import numpy as np
+        v = np.zeros(N_BINS, dtype=np.float32)
+        _check(lib().gc_graph_count_times(self.handle, ctypes.c_void_p(v.ctypes.data), N_BINS),
+               "gc_graph_count_times")
+        return v
 
     def truss_stats(self) -> dict:
         """Counters of the last truss decomposition on this handle."""

@@ -204,10 +204,19 @@ extern "C" gc_status gc_triangle_count(gc_graph *g, gc_stream stream, int64_t *h
     GC_TRY(g->ws.reserve(256));
     unsigned long long *d = g->ws.take<unsigned long long>(1);
     GC_HIP(hipMemsetAsync(d, 0, sizeof(unsigned long long), s));
-    GC_TRY(count_triangles_ex(c, g->units, d, nullptr, nullptr, g->strategy, s));
+    // one launch per degree bin, each bracketed by events for gc_graph_count_times
+    for (hipEvent_t &e : g->count_ev)
+      if (!e) GC_HIP(hipEventCreate(&e));
+    GC_HIP(hipEventRecord(g->count_ev[0], s));
+    for (int b = 0; b < kCountBins; ++b) {
+      GC_TRY(count_bin(c, g->units, b, g->strategy[b], d, nullptr, nullptr, s));
+      GC_HIP(hipEventRecord(g->count_ev[b + 1], s));
+    }
     unsigned long long h = 0;
     GC_HIP(hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, s));
     GC_HIP(hipStreamSynchronize(s));
+    for (int b = 0; b < kCountBins; ++b)
+      GC_HIP(hipEventElapsedTime(&g->count_ms[b], g->count_ev[b], g->count_ev[b + 1]));
     *h_count = (int64_t)h;
     return GC_OK;
   });
@@ -251,6 +260,16 @@ extern "C" gc_status gc_graph_truss_stats(const gc_graph *g, int64_t *h_stats, i
   }
   constexpr int32_t kStats = (int32_t)(sizeof(g->peel_stats) / sizeof(g->peel_stats[0]));
   for (int32_t i = 0; i < cap && i < kStats; ++i) h_stats[i] = g->peel_stats[i];
+  return GC_OK;
+}
+
+extern "C" gc_status gc_graph_count_times(const gc_graph *g, float *h_ms, int32_t cap) {
+  clear_error();
+  if (!g || !h_ms || cap < 0) {
+    set_error("gc_graph_count_times: invalid argument");
+    return GC_EINVAL;
+  }
+  for (int32_t b = 0; b < cap && b < kCountBins; ++b) h_ms[b] = g->count_ms[b];
   return GC_OK;
 }
 

@@ -82,6 +82,10 @@ struct gc_graph {
   // floor(log2(frontier size)), [37] candidates examined, [38] searched,
   // [39] triangles found, [40] triangles destroyed (subtracted)
   int64_t peel_stats[41] = {0};
+  // duration of each degree bin's count launch in the last gc_triangle_count
+  // (HIP events around the launches on the call's stream; -1 before one)
+  hipEvent_t count_ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  float count_ms[5] = {-1.f, -1.f, -1.f, -1.f, -1.f};
   template <class F>
   void each_buffer(F &&f) const {
     for (const gc::DeviceBuffer *b : {&u, &v, &rank, &vid, &units.units, &units_sup.units, &ws.buf,
@@ -110,6 +114,11 @@ struct gc_graph {
     gc::dfree(units.units); gc::dfree(units_sup.units); gc::dfree(work_units.units);
     gc::dfree(t_sup); gc::dfree(t_flag); gc::dfree(t_pos); gc::dfree(t_misc);
     gc::dfree(ws.buf);
+    for (hipEvent_t &e : count_ev)
+      if (e) {
+        (void)hipEventDestroy(e);
+        e = nullptr;
+      }
   }
 };
 

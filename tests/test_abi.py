@@ -96,6 +96,7 @@ def test_null_handles_rejected_on_the_host(lib):
         ("gc_graph_autotune", [P, P, P, P], [None, None, None, None]),
         ("gc_graph_set_strategy", [P, P], [None, None]),
         ("gc_graph_truss_stats", [P, P, I32], [None, None, 0]),
+        ("gc_graph_count_times", [P, P, I32], [None, None, 0]),
         ("gc_batch_info", [P, P, P, P], [None, None, None, None]),
         ("gc_batch_edge_offsets", [P, P], [None, None]),
         ("gc_batch_triangle_count", [P, P, P], [None, None, None]),

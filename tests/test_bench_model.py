@@ -95,3 +95,15 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_count_kernel_names_follow_the_dispatch_table():
+    """The roofline names the kernel a degree bin runs under its strategy, as
+    the library's dispatch does (include/gc.h lists the strategies)."""
+    k = bench.count_kernel_name
+    assert k(2, 3) == "gc::k_tc_lds<gc::BucketTable<10> >"
+    assert k(1, 4) == "gc::k_tc_lds<gc::BucketTable<8> >"
+    assert k(0, 5) == "gc::k_tc_group<6, 16>" and k(1, 5) == "gc::k_tc_group<9, 64>"
+    assert k(2, 0) == "gc::k_tc_lds<gc::LinTable<12> >"
+    assert k(3, 1) == "gc::k_tc_lds<gc::LinTable<15> >"
+    assert k(4, 2) == "gc::k_tc_search" and k(2, 2) == "gc::k_tc_search"
