@@ -528,6 +528,54 @@ def bench_serve(gc, n_graphs: int, n_requests: int, big_max: int, budget: int) -
     }
 
 
+def bench_contrast(gc, torch, dev, scale: int, ef: int, seed: int, steps: int) -> dict:
+    """The paired contrast of the full-size workload: an Erdos-Renyi G(n, M)
+    graph with n = 2^scale and M = ef * n pairs (mean degree about 2 ef, low
+    clustering), the same step (build + count + full decomposition), after
+    autotuning the count on it and one untimed step."""
+    import graphgen as gg
+    t = time.perf_counter()
+    n = 1 << scale
+    src, dst = gg.er(n, ef * n, seed=seed)[:2]
+    log("contrast: generated %d ER pairs in %.1fs" % (len(src), time.perf_counter() - t))
+    d_src = torch.from_numpy(src).to(dev)
+    d_dst = torch.from_numpy(dst).to(dev)
+    del src, dst
+    g = gc.gc_build_csr(d_src, d_dst, n)
+    strategy, _ = g.autotune()
+    g.free()
+    stream = torch.cuda.current_stream()
+    tau = None
+    rows = []
+    for i in range(steps + 1):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev[0].record(stream)
+        g = gc.gc_build_csr(d_src, d_dst, n)
+        ev[1].record(stream)
+        T = g.triangle_count()
+        ev[2].record(stream)
+        if tau is None:
+            tau = torch.empty(max(g.m, 1), dtype=torch.int32, device=dev)
+        _, kmax = g.truss_decomposition(out=tau)
+        ev[3].record(stream)
+        torch.cuda.synchronize()
+        m = g.m
+        bins = g.count_times()
+        g.free()
+        if i > 0:
+            rows.append([ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]),
+                         ev[2].elapsed_time(ev[3]), ev[0].elapsed_time(ev[3])] + list(bins))
+    r = np.mean(np.array(rows), axis=0)
+    return {"workload": "Erdos-Renyi G(n, M), n = 2^%d, M = %d n pairs, seed %d; step = build "
+                        "CSR + triangle count + full truss decomposition" % (scale, ef, seed),
+            "m_edges": int(m), "triangles": int(T), "kmax": int(kmax),
+            "edges_per_s": m / (r[3] / 1000.0), "ms_per_step": float(r[3]),
+            "phases_ms": {"build": float(r[0]), "triangle_count": float(r[1]),
+                          "decomposition": float(r[2])},
+            "count_ms_by_bin": [float(x) for x in r[4:]],
+            "autotuned_strategy": strategy.tolist(), "steps": steps}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -548,6 +596,8 @@ def main():
                     help="step = build + count only")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the per-bin strategy autotuner (run before the timed steps)")
+    ap.add_argument("--contrast-steps", type=int, default=2,
+                    help="timed steps of the Erdos-Renyi contrast of the same size (0 = skip)")
     ap.add_argument("--batch-graphs", type=int, default=4096,
                     help="graphs in the batched-path comparison (0: skip)")
     ap.add_argument("--batch-max-scale", type=int, default=16)
@@ -793,6 +843,13 @@ def main():
             "frac_of_achievable_copy": achieved / bw["copy_GBps"],
         },
     }
+    del d_src, d_dst
+    torch.cuda.empty_cache()
+    if args.contrast_steps > 0 and not args.input and args.workload == "rmat":
+        log("contrast: Erdos-Renyi n = 2^%d ..." % args.scale)
+        out["er_contrast"] = bench_contrast(gc, torch, dev, args.scale, args.ef, 2,
+                                            args.contrast_steps)
+        log("contrast: %s" % json.dumps(out["er_contrast"]))
     if args.batch_graphs > 0:
         log("batched path: %d graphs ..." % args.batch_graphs)
         out["batch"] = bench_batch(gc, torch, dev, args.batch_graphs, args.batch_max_scale)

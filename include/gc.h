@@ -162,6 +162,9 @@ gc_status gc_ktruss(gc_graph *g, int32_t k, uint8_t *d_in_truss, int64_t cap,
  *   5 a group of lanes per work unit (16 in bin 0, a wavefront in bin 1)
  *     with its own LDS table, one lane per in-edge (bins 0 and 1 only: many
  *     small units)
+ *   6 merge: the group copies the sorted N+(b) to LDS and each lane merges
+ *     the sorted tail of an in-edge with it by two pointers (bins 0 and 1
+ *     only: short lists on both sides)
  * Results never depend on the strategy.  A new handle takes them from the
  * file named by the environment variable GC_AUTOTUNE_CACHE if it exists
  * (lines "<arch> <bin> <strategy>"), else {0, 0, 0, 0, 2}. */
@@ -169,7 +172,7 @@ gc_status gc_ktruss(gc_graph *g, int32_t k, uint8_t *d_in_truss, int64_t cap,
 /* Autotuner: time every admissible strategy of every bin that has work on
  * this graph (HIP events, first run discarded), keep the fastest per bin and,
  * if GC_AUTOTUNE_CACHE is set, write the choices there.  h_strategy[5] and
- * h_ms[5*6] (mean ms per bin and strategy, row-major by bin; -1 where not
+ * h_ms[5*7] (mean ms per bin and strategy, row-major by bin; -1 where not
  * run) may be NULL.
  * Synchronises `stream`. */
 gc_status gc_graph_autotune(gc_graph *g, gc_stream stream, int32_t *h_strategy,
@@ -269,7 +272,7 @@ gc_status gc_batch_ktruss(gc_batch *b, int32_t k, uint8_t *d_mask, int64_t cap,
 /* Autotuner of a batch, as gc_graph_autotune (strategies listed there):
  * times every admissible count strategy per degree bin on the whole batch,
  * keeps the fastest, writes GC_AUTOTUNE_CACHE if set.  h_strategy[5] and
- * h_ms[5*6] may be NULL.  Results never depend on the choice. */
+ * h_ms[5*7] may be NULL.  Results never depend on the choice. */
 gc_status gc_batch_autotune(gc_batch *b, gc_stream stream, int32_t *h_strategy,
                             float *h_ms);
 

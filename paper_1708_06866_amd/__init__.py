@@ -47,7 +47,7 @@ GC_PENDING = 1
 
 # count strategies: N_BINS degree bins, N_STRATEGIES strategies (include/gc.h)
 N_BINS = 5
-N_STRATEGIES = 6
+N_STRATEGIES = 7
 
 _lib = None
 
@@ -262,7 +262,7 @@ class Graph:
         return gc_truss_decomposition(self, out, stream)
 
     def autotune(self, stream=None):
-        """Per-bin count strategies chosen by timing: (strategy[5], ms[5, 6])."""
+        """Per-bin count strategies chosen by timing: (strategy[5], ms[5, 7])."""
         import numpy as np
         st = np.zeros(5, dtype=np.int32)
         ms = np.zeros(N_BINS * N_STRATEGIES, dtype=np.float32)

@@ -23,7 +23,8 @@
 // count_strategy_valid): either layout with at most half or a quarter of the
 // slots used, binary search of N+(b) in HBM (the only one for the last,
 // unbounded bin), or for bins 0 and 1 a lane group per unit with its own
-// table.  The autotuner times them per bin on the graph at hand.
+// table, or a merge of each tail with N+(b).  The autotuner times them per
+// bin on the graph at hand.
 //
 // Support: a hit (a, b, c) adds one to each of its three edges.  a -> b (the
 // in-edge) is counted in an LDS counter per packed in-edge and added once per
@@ -425,6 +426,52 @@ __global__ __launch_bounds__(CBLK) void k_tc_group(CsrView c, const int4 *__rest
   }
 }
 
+// Merge (strategy 6, bins 0 and 1): a group of GL lanes per unit copies the
+// sorted N+(b) (at most MAXD entries) to LDS, and each lane takes whole
+// in-edges a -> b, merging the sorted tail of a's row with it by two
+// pointers: |tail(a) cap N+(b)| in at most |tail| + d+(b) steps.  No hashing
+// and no search; suits short lists on both sides.
+template <int MAXD, int GL>
+__global__ __launch_bounds__(CBLK) void k_tc_merge(CsrView c, const int4 *__restrict__ units,
+                                                   int64_t nunits, CountOut out) {
+  constexpr int GPB = CBLK / GL;  // groups per block
+  __shared__ int32_t rows[GPB][MAXD];
+  const int gl = threadIdx.x % GL;
+  int32_t *row = rows[threadIdx.x / GL];
+  const int64_t gid = ((int64_t)blockIdx.x * CBLK + threadIdx.x) / GL;
+  const int64_t ng = (int64_t)gridDim.x * GPB;
+  int32_t hits = 0;  // over every unit of this lane (total count)
+  for (int64_t ui = gid; ui < nunits; ui += ng) {
+    const int4 U = units[ui];
+    const int32_t rb = c.row_ptr[U.x], d = c.row_ptr[U.x + 1] - rb;
+    for (int32_t i = gl; i < d; i += GL) row[i] = c.col[rb + i];
+    wave_lds_sync();
+    int32_t mine = 0;
+    for (int32_t j = U.y + gl; j < U.z; j += GL) {
+      const int2 t = c.in_tail[j];
+      int32_t i = t.x, k = 0;
+      while (i < t.y && k < d) {
+        const int32_t x = c.col[i], y = row[k];
+        i += x <= y ? 1 : 0;
+        k += y <= x ? 1 : 0;
+        mine += x == y ? 1 : 0;
+      }
+    }
+    if (out.per_graph) {
+      for (int o = GL / 2; o > 0; o >>= 1) mine += __shfl_xor(mine, o, GL);
+      if (gl == 0 && mine)
+        atomicAdd(&out.per_graph[out.graph_of_rank[U.x]], (unsigned long long)mine);
+    } else {
+      hits += mine;
+    }
+    wave_lds_sync();  // the group is done with the row before it is overwritten
+  }
+  if (!out.per_graph) {
+    const int32_t sum = wave_sum_i32(hits);
+    if ((threadIdx.x & 63) == 0 && sum) atomicAdd(out.total, (unsigned long long)sum);
+  }
+}
+
 // Out-lists too long for LDS: binary search in the sorted row in HBM.
 __global__ __launch_bounds__(CBLK) void k_tc_search(CsrView c, const int4 *__restrict__ units,
                                                     int64_t nunits, CountOut out) {
@@ -467,10 +514,11 @@ static unsigned unit_grid(int64_t nunits, int per_cu) {
 //   2 binary search in HBM                  3 bucketed table, load <= 1/2
 //   4 bucketed table, load <= 1/4           5 one wave per unit, own table
 //                                             (bins 0 and 1 only)
+//   6 merge of each tail with N+(b) (bins 0 and 1 only)
 // The last (unbounded) bin only admits 2.
 bool count_strategy_valid(int bin, int strategy) {
   if (strategy == 2) return true;
-  if (strategy == 5) return bin <= 1;
+  if (strategy == 5 || strategy == 6) return bin <= 1;
   return bin < NBINS - 1 && strategy >= 0 && strategy < kCountStrategies;
 }
 
@@ -500,6 +548,11 @@ static gc_status launch_count_bin(const CsrView &c, const int4 *ub, int64_t nu, 
       k_tc_group<6, 16><<<unit_grid((nu + 15) / 16, 16), CBLK, 0, s>>>(c, ub, nu, o);
     else         // d+ <= 256: a wave per unit
       k_tc_group<9, 64><<<unit_grid((nu + 3) / 4, 16), CBLK, 0, s>>>(c, ub, nu, o);
+  } else if (strategy == 6) {
+    if (b == 0)  // d+ <= 32: groups of 16 lanes
+      k_tc_merge<32, 16><<<unit_grid((nu + 15) / 16, 16), CBLK, 0, s>>>(c, ub, nu, o);
+    else         // d+ <= 256: a wave per unit
+      k_tc_merge<256, 64><<<unit_grid((nu + 3) / 4, 16), CBLK, 0, s>>>(c, ub, nu, o);
   } else if (strategy == 0 || strategy == 1) {
     switch (bin_logs_count(b) + (strategy == 1 ? 1 : 0)) {
       case 6: launch_tc_lds<LinTable<6>>(c, ub, nu, o, s); break;

@@ -135,8 +135,9 @@ gc_status count_triangles(const CsrView &c, const UnitStore &u, unsigned long lo
                           hipStream_t s);
 constexpr int kCountBins = 5;
 // 0/1 linear-probing LDS table (load <= 1/2, 1/4), 2 binary search in HBM,
-// 3/4 bucketed LDS table (load <= 1/2, 1/4), 5 one wave per unit (bins 0, 1)
-constexpr int kCountStrategies = 6;
+// 3/4 bucketed LDS table (load <= 1/2, 1/4), 5 one wave per unit (bins 0, 1),
+// 6 merge of sorted lists (bins 0, 1)
+constexpr int kCountStrategies = 7;
 bool count_strategy_valid(int bin, int strategy);
 // Count with a chosen strategy per bin (strategy may be null = defaults); per
 // graph counts if d_per_graph != null (graph_of_rank maps a rank to its graph).

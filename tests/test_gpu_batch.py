@@ -89,7 +89,8 @@ def test_every_strategy_same_counts():
     b = gc.build_batch(graphs)
     base = b.triangle_count().cpu().numpy().copy()
     for st in ([0, 0, 0, 0, 2], [1, 1, 1, 1, 2], [2, 2, 2, 2, 2], [3, 3, 3, 3, 2],
-               [4, 4, 4, 4, 2], [0, 1, 2, 3, 2], [4, 3, 1, 0, 2], [5, 5, 3, 4, 2]):
+               [4, 4, 4, 4, 2], [0, 1, 2, 3, 2], [4, 3, 1, 0, 2], [5, 5, 3, 4, 2],
+               [6, 6, 3, 4, 2]):
         b.set_strategy(st)
         assert np.array_equal(b.triangle_count().cpu().numpy(), base), st
     chosen, ms = b.autotune()

@@ -433,7 +433,8 @@ def test_ktruss_peel_equals_rounds(monkeypatch):
 
 
 @pytest.mark.parametrize("strategy", [[0, 0, 0, 0, 2], [1, 1, 1, 1, 2], [2, 2, 2, 2, 2],
-                                      [3, 3, 3, 3, 2], [4, 4, 4, 4, 2], [5, 5, 0, 0, 2]])
+                                      [3, 3, 3, 3, 2], [4, 4, 4, 4, 2], [5, 5, 0, 0, 2],
+                                      [6, 6, 3, 3, 2], [6, 5, 0, 0, 2]])
 def test_count_strategies_agree(strategy):
     """Every count strategy gives the oracle's count (bins 0-3 exercised by the
     R-MAT graph and a complete graph reaching d+ > 2048)."""
@@ -459,6 +460,8 @@ def test_autotune_keeps_counts():
         g.set_strategy([0, 0, 0, 0, 1])
     with pytest.raises(gc.GCError):
         g.set_strategy([0, 0, 5, 0, 2])   # one wave per unit only for bins 0 and 1
+    with pytest.raises(gc.GCError):
+        g.set_strategy([0, 0, 6, 0, 2])   # merge only for bins 0 and 1
     g.free()
 
 
