@@ -10,7 +10,8 @@
 // of its waves lays the tails of its in-edges of the chunk end to end and
 // streams that concatenation, 64 consecutive elements per load (coalesced
 // within a tail), 4 loads in flight per lane, so short tails do not leave
-// lanes idle.
+// lanes idle; a lane finds the tail of its next element by stepping on from
+// the tail of its last one.
 //
 // Two LDS table layouts: linear probing over single slots (LinTable), and
 // buckets of 4 slots in 16 bytes, filled in slot order, with linear probing
@@ -171,17 +172,31 @@ __device__ __forceinline__ void pack_tails(const CsrView &c, int32_t j0, int32_t
   total = __shfl(incl, 63, 64);
 }
 
-// Tail element number t of the packing: its position in col (and in *kk,
-// the number of its in-edge in the packing).
-__device__ __forceinline__ int32_t packed_pos(const int32_t *offs, const int32_t *xs, int32_t t,
-                                              int *kk = nullptr) {
-  int k = 0;
-#pragma unroll
-  for (int s = TC_PACK / 2; s > 0; s >>= 1)
-    if (offs[k + s] <= t) k += s;
-  if (kk) *kk = k;
-  return xs[k] + (t - offs[k]);
-}
+// Position in col of tail element number t of the packing, for t that only
+// grows from one call to the next (a lane's elements are base + 64 u + lane,
+// in order): the in-edge whose tail holds t is found by stepping on from the
+// previous one (k, its first element off_k and position x_k, and the next
+// tail's first element), so a lane reads LDS only when it crosses into
+// another tail, at most TC_PACK times per packing.  Empty tails (equal
+// offsets) are stepped over.
+struct PackCursor {
+  int32_t k, off_k, x_k, off_next;
+  __device__ __forceinline__ void init(const int32_t *offs, const int32_t *xs) {
+    k = 0;
+    off_k = offs[0];
+    x_k = xs[0];
+    off_next = TC_PACK > 1 ? offs[1] : 0x7fffffff;
+  }
+  __device__ __forceinline__ int32_t pos(const int32_t *offs, const int32_t *xs, int32_t t) {
+    while (t >= off_next) {
+      ++k;
+      off_k = off_next;
+      x_k = xs[k];
+      off_next = k + 1 < TC_PACK ? offs[k + 1] : 0x7fffffff;
+    }
+    return x_k + (t - off_k);
+  }
+};
 
 template <class TB>
 __device__ __forceinline__ int32_t probe_packed(const int32_t *tab, const CsrView &c, int32_t j0,
@@ -191,20 +206,22 @@ __device__ __forceinline__ int32_t probe_packed(const int32_t *tab, const CsrVie
   pack_tails(c, j0, j1, lane, offs, xs, total);
   wave_lds_sync();
   int32_t hits = 0;
+  PackCursor cur;
+  cur.init(offs, xs);
   // (the tails are in distinct rows, so total <= m < 2^31; positions past it
   // are formed in 64 bits)
   int32_t w[TC_UNROLL];
 #pragma unroll
   for (int u = 0; u < TC_UNROLL; ++u) {
     const int32_t t = 64 * u + lane;
-    w[u] = t < total ? c.col[packed_pos(offs, xs, t)] : -1;
+    w[u] = t < total ? c.col[cur.pos(offs, xs, t)] : -1;
   }
   for (int64_t base = 0; base < total; base += 64 * TC_UNROLL) {
     int32_t wn[TC_UNROLL];
 #pragma unroll
     for (int u = 0; u < TC_UNROLL; ++u) {  // the next step, in flight while we probe
       const int64_t t = base + 64 * TC_UNROLL + 64 * u + lane;
-      wn[u] = t < total ? c.col[packed_pos(offs, xs, (int32_t)t)] : -1;
+      wn[u] = t < total ? c.col[cur.pos(offs, xs, (int32_t)t)] : -1;
     }
     typename TB::Probe q[TC_UNROLL];
 #pragma unroll
@@ -819,6 +836,8 @@ __global__ __launch_bounds__(CBLK) void k_sup_lds(CsrView c, const int4 *__restr
     int32_t total;
     pack_tails(c, U.y + wave, U.z, lane, offs, xs, total);
     wave_lds_sync();
+    PackCursor cur;
+    cur.init(offs, xs);
     for (int64_t base = 0; base < total; base += 64 * TC_UNROLL) {
       int32_t w[TC_UNROLL], pp[TC_UNROLL], kk[TC_UNROLL];
 #pragma unroll
@@ -826,7 +845,8 @@ __global__ __launch_bounds__(CBLK) void k_sup_lds(CsrView c, const int4 *__restr
         const int64_t t = base + 64 * u + lane;
         w[u] = -1;
         if (t < total) {
-          pp[u] = packed_pos(offs, xs, (int32_t)t, &kk[u]);
+          pp[u] = cur.pos(offs, xs, (int32_t)t);
+          kk[u] = cur.k;
           w[u] = c.col[pp[u]];
         }
       }
