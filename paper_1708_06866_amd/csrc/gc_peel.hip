@@ -214,6 +214,21 @@ __device__ __forceinline__ void wave_lds_fence() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Edge of the batch holding candidate t for t that only grows from one call
+// to the next: stepped on from the last one.
+struct BatchCursor {
+  int e;
+  long long next;
+  __device__ __forceinline__ void init(const PeelBatch &B) { e = 0; next = B.off[1]; }
+  __device__ __forceinline__ int edge(const PeelBatch &B, long long t) {
+    while (t >= next) {
+      ++e;
+      next = e < 63 ? B.off[e + 1] : 0x7fffffffffffffffLL;
+    }
+    return e;
+  }
+};
+
 // Edge of the batch holding candidate t (the last e with off[e] <= t).
 __device__ __forceinline__ int batch_edge(const PeelBatch &B, long long t) {
   int e = 0;
@@ -349,6 +364,8 @@ __global__ __launch_bounds__(PBLK) void k_peel(CsrView c, const int32_t *__restr
       wave_lds_fence();
       // ---- the concatenated candidates, 64 * PEEL_U per step ----
       long long base = 0;
+      BatchCursor cur;
+      cur.init(B);
       for (;;) {
         // skip edges that have seen all their triangles
         while (base < T) {
@@ -370,7 +387,7 @@ __global__ __launch_bounds__(PBLK) void k_peel(CsrView c, const int32_t *__restr
           bin[u] = false;
           act[u] = false;
           if (t < T) {
-            const int e = batch_edge(B, t);
+            const int e = cur.edge(B, t);
             eu[u] = e;
             if (B.seen[e] < B.need[e]) {
               const int32_t local = (int32_t)(t - B.off[e]);
@@ -581,8 +598,8 @@ __global__ __launch_bounds__(256) void k_collect_tiles(int32_t m, int32_t thr,
                                                        const int32_t *__restrict__ sup,
                                                        int32_t *__restrict__ tmp,
                                                        int32_t *__restrict__ tile_cnt,
-                                                       int32_t *__restrict__ dmin,
-                                                       int32_t *__restrict__ dalive) {
+                                                       int32_t *__restrict__ tile_min,
+                                                       int32_t *__restrict__ tile_live) {
   __shared__ int32_t wtot[4], wmin[4], wlive[4];
   const int64_t tile0 = (int64_t)blockIdx.x * CT_TILE;
   const int64_t i0 = tile0 + (int64_t)threadIdx.x * CT_PER;
@@ -622,7 +639,7 @@ __global__ __launch_bounds__(256) void k_collect_tiles(int32_t m, int32_t thr,
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int32_t incl = wave_inclusive_scan(cnt);
   if (lane == 63) wtot[w] = incl;
-  if (dmin) {
+  if (tile_min) {
     for (int o = 32; o > 0; o >>= 1) {
       vmin = min(vmin, __shfl_xor(vmin, o, 64));
       live += __shfl_xor(live, o, 64);
@@ -633,13 +650,12 @@ __global__ __launch_bounds__(256) void k_collect_tiles(int32_t m, int32_t thr,
     }
   }
   __syncthreads();
-  if (dmin && threadIdx.x == 0) {
-    const int32_t bm = min(min(wmin[0], wmin[1]), min(wmin[2], wmin[3]));
-    const int32_t bl = wlive[0] + wlive[1] + wlive[2] + wlive[3];
-    if (bl > 0) {
-      atomicMin(dmin, bm);
-      atomicAdd(dalive, bl);
-    }
+  if (tile_min && threadIdx.x == 0) {
+    // per tile: one atomic per tile on a single address serialises the
+    // tiles (62 ms of a scale-24 decomposition), so the minimum and count
+    // are reduced by k_min_live instead
+    tile_min[blockIdx.x] = min(min(wmin[0], wmin[1]), min(wmin[2], wmin[3]));
+    tile_live[blockIdx.x] = wlive[0] + wlive[1] + wlive[2] + wlive[3];
   }
   int32_t off = incl - cnt;
   for (int i = 0; i < w; ++i) off += wtot[i];
@@ -651,6 +667,40 @@ __global__ __launch_bounds__(256) void k_collect_tiles(int32_t m, int32_t thr,
       state[i0 + k] = EDGE_FRONT;
       *out++ = (int32_t)(i0 + k);
     }
+}
+
+// dmin = the smallest of tile_min[0, n), dalive = the sum of tile_live[0, n)
+// (one block).
+__global__ __launch_bounds__(1024) void k_min_live(const int32_t *__restrict__ tile_min,
+                                                   const int32_t *__restrict__ tile_live,
+                                                   int32_t n, int32_t *__restrict__ dmin,
+                                                   int32_t *__restrict__ dalive) {
+  __shared__ int32_t smin[16], slive[16];
+  int32_t vmin = 0x7fffffff, live = 0;
+  for (int32_t i = threadIdx.x; i < n; i += 1024) {
+    vmin = min(vmin, tile_min[i]);
+    live += tile_live[i];
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    vmin = min(vmin, __shfl_xor(vmin, o, 64));
+    live += __shfl_xor(live, o, 64);
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    smin[w] = vmin;
+    slive[w] = live;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    vmin = smin[0];
+    live = slive[0];
+    for (int i = 1; i < 16; ++i) {
+      vmin = min(vmin, smin[i]);
+      live += slive[i];
+    }
+    *dmin = vmin;
+    *dalive = live;
+  }
 }
 
 // Copy tile b's tile_cnt[b] entries of tmp to front[tile_pos[b] ...).
@@ -844,8 +894,8 @@ gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStre
     GC_TRY(dalloc(ps.front[i], sizeof(int32_t) * ((size_t)m + 1)));
   }
   GC_TRY(dalloc(ps.flag, sizeof(int32_t) * ((size_t)m + 1)));
-  // (m + 2 for the scans over slots; the level start also keeps two arrays of
-  // tile counts there, 2 * ceil(m / CT_TILE) + 2 <= m + 64 entries)
+  // (m + 2 for the scans over slots; the level start also keeps four arrays
+  // of per-tile values there, 4 * (ceil(m / CT_TILE) + 1) <= m + 64 entries)
   GC_TRY(dalloc(ps.pos, sizeof(int32_t) * ((size_t)m + 64)));
   GC_TRY(dalloc(ps.misc, 256));
   int32_t *misc = static_cast<int32_t *>(ps.misc.ptr);  // [0] count, [1] min
@@ -940,8 +990,14 @@ gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStre
     auto collect = [&](int32_t t, int32_t *dmin, int32_t *dalive) -> gc_status {
       const int32_t ntiles = (int32_t)(((int64_t)c.m + CT_TILE - 1) / CT_TILE);
       int32_t *tile_cnt = pos, *tile_pos = pos + ntiles + 1;
-      k_collect_tiles<<<ntiles, 256, 0, s>>>(c.m, t, state, sup, flag, tile_cnt, dmin, dalive);
+      int32_t *tile_min = pos + 2 * (ntiles + 1), *tile_live = pos + 3 * (ntiles + 1);
+      k_collect_tiles<<<ntiles, 256, 0, s>>>(c.m, t, state, sup, flag, tile_cnt,
+                                             dmin ? tile_min : nullptr, tile_live);
       GC_LAUNCH_CHECK();
+      if (dmin) {
+        k_min_live<<<1, 1024, 0, s>>>(tile_min, tile_live, ntiles, dmin, dalive);
+        GC_LAUNCH_CHECK();
+      }
       GC_TRY(g->ws.reserve(scan_scratch_bytes((int64_t)ntiles + 1)));
       GC_TRY(exclusive_scan(tile_cnt, tile_pos, ntiles,
                             g->ws.take<char>(scan_scratch_bytes((int64_t)ntiles + 1)), s));
