@@ -265,7 +265,14 @@ gc_status gc_batch_edge_support(gc_batch *b, int32_t *d_support, int64_t cap,
 
 /* k-truss of every graph (Sec. III-B, Alg. 4): d_mask[e] in batch edge order
  * (device, uint8, Σm entries) and d_mk[g] = edges in graph g's k-truss
- * (device, int64, G entries).  Synchronises `stream`. */
+ * (device, int64, G entries).  For 3 <= k <= 66 the launches (support, then
+ * levels 3 .. k of the peeling with a fixed number of rounds each, the mask
+ * and the per-graph counts) are recorded into a HIP graph on the first call
+ * for that k and replayed afterwards; if a level needed more rounds than
+ * were recorded, the call peels eagerly instead (same result) and the next
+ * call records twice the rounds.  Rounds first recorded per level: 32, or
+ * the environment variable GC_BATCH_KTRUSS_ROUNDS read when the batch is
+ * built.  cap < Σm gives GC_ECAPACITY.  Synchronises `stream`. */
 gc_status gc_batch_ktruss(gc_batch *b, int32_t k, uint8_t *d_mask, int64_t cap,
                           int64_t *d_mk, gc_stream stream);
 

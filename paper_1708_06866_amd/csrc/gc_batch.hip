@@ -39,12 +39,26 @@ struct gc_batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipStream_t own_stream = nullptr;  // capture stream when the caller passes the null stream
+  // the k-truss of every graph as a second recorded launch sequence
+  gc::PeelReplay kt;
+  gc::DeviceBuffer kt_mask, kt_cnt;  // its mask (uint8 [m]) and per-graph sizes (u64 [G])
+  int32_t kt_k = 0;                  // k it was recorded for
+  int32_t kt_rounds = 32;            // rounds recorded per level
+  hipGraph_t kt_graph = nullptr;
+  hipGraphExec_t kt_exec = nullptr;
   void drop_graph() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     exec = nullptr;
     graph = nullptr;
     captured = false;
+  }
+  void drop_kt_graph() {
+    if (kt_exec) (void)hipGraphExecDestroy(kt_exec);
+    if (kt_graph) (void)hipGraphDestroy(kt_graph);
+    kt_exec = nullptr;
+    kt_graph = nullptr;
+    kt_k = 0;
   }
 };
 
@@ -273,6 +287,11 @@ extern "C" gc_status gc_batch_build(const int32_t *d_src, const int32_t *d_dst,
       hipStreamSynchronize(s) != hipSuccess)
     return fail(GC_EDEVICE);
   load_strategy_cache(b->device, b->strategy);
+  // rounds recorded per level of the replayed k-truss (GC_BATCH_KTRUSS_ROUNDS)
+  if (const char *ev = getenv("GC_BATCH_KTRUSS_ROUNDS")) {
+    const long r = strtol(ev, nullptr, 10);
+    if (r >= 1 && r <= 4096) b->kt_rounds = (int32_t)r;
+  }
   *out = b;
   return GC_OK;
 }
@@ -394,14 +413,94 @@ extern "C" gc_status gc_batch_edge_support(gc_batch *b, int32_t *d_support, int6
   return gc_edge_support(b->g, d_support, cap, stream);
 }
 
+namespace gc {
+
+// The k-truss of every graph of the batch from the recorded launch sequence
+// (recorded on the first call for this k): levels 3 .. k of the peeling, a
+// fixed number of rounds each, then the union's mask and each graph's count.
+// Returns GC_OK with *converged false when a level needed more rounds than
+// were recorded (the caller then peels eagerly, and the next call records
+// twice the rounds).
+static gc_status batch_ktruss_replay(gc_batch *b, int32_t k, hipStream_t s, hipStream_t cs,
+                                     bool *converged) {
+  gc_graph *g = b->g;
+  *converged = false;
+  if (!b->kt_exec || b->kt_k != k) {
+    b->drop_kt_graph();
+    GC_TRY(b->kt.prepare((int32_t)g->m));
+    GC_TRY(dalloc(b->kt_mask, (size_t)g->m + 1));
+    GC_TRY(dalloc(b->kt_cnt, sizeof(unsigned long long) * ((size_t)b->G + 1)));
+    GC_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    unsigned long long *cnt = static_cast<unsigned long long *>(b->kt_cnt.ptr);
+    uint8_t *mask = static_cast<uint8_t *>(b->kt_mask.ptr);
+    gc_status st = ktruss_launches(g, k, b->kt_rounds, b->kt, mask, cs);
+    if (st == GC_OK) {
+      k_zero_u64<<<gsz(b->G), 256, 0, cs>>>(cnt, b->G);
+      k_mask_counts<<<gsz(g->m), 256, 0, cs>>>(mask, static_cast<const int32_t *>(g->u.ptr), g->m,
+                                              static_cast<const int32_t *>(b->vbase.ptr), b->G,
+                                              cnt);
+      if (hipGetLastError() != hipSuccess) st = GC_EDEVICE;
+    }
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(cs, &graph);
+    if (st != GC_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st;
+    }
+    GC_HIP(e);
+    b->kt_graph = graph;
+    GC_HIP(hipGraphInstantiate(&b->kt_exec, graph, nullptr, nullptr, 0));
+    b->kt_k = k;
+  }
+  GC_HIP(hipGraphLaunch(b->kt_exec, cs));
+  int32_t left[64];
+  GC_HIP(hipMemcpyAsync(left, b->kt.leftover(), sizeof(int32_t) * (k - 2), hipMemcpyDeviceToHost,
+                        cs));
+  GC_HIP(hipStreamSynchronize(cs));
+  (void)s;
+  bool all = true;
+  for (int32_t i = 0; i < k - 2; ++i) all = all && left[i] == 0;
+  *converged = all;
+  return GC_OK;
+}
+
+}  // namespace gc
+
 extern "C" gc_status gc_batch_ktruss(gc_batch *b, int32_t k, uint8_t *d_mask, int64_t cap,
                                      int64_t *d_mk, gc_stream stream) {
   clear_error();
-  if (!b || (b->G > 0 && !d_mk)) {
+  if (!b || (b->G > 0 && !d_mk) || k < 2 || (b->g && b->g->m > 0 && !d_mask)) {
     set_error("gc_batch_ktruss: invalid argument");
     return GC_EINVAL;
   }
+  if (b->g && cap < b->g->m) {
+    set_error("gc_batch_ktruss: cap < m");
+    return GC_ECAPACITY;
+  }
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (b->G > 0 && b->g->m > 0 && k > 2 && k - 2 <= 64) {
+    // the recorded sequence, on the caller's stream (or an own blocking one
+    // for the null stream, which cannot be captured)
+    hipStream_t cs = s;
+    if (!cs) {
+      if (!b->own_stream) GC_HIP(hipStreamCreate(&b->own_stream));
+      cs = b->own_stream;
+    }
+    bool converged = false;
+    GC_TRY(batch_ktruss_replay(b, k, s, cs, &converged));
+    if (converged) {
+      GC_HIP(hipMemcpyAsync(d_mask, b->kt_mask.ptr, (size_t)b->g->m, hipMemcpyDeviceToDevice, s));
+      k_copy_u64<<<gsz(b->G), 256, 0, s>>>(static_cast<const unsigned long long *>(b->kt_cnt.ptr),
+                                           b->G, d_mk);
+      GC_LAUNCH_CHECK();
+      GC_HIP(hipStreamSynchronize(s));
+      return GC_OK;
+    }
+    // a level needed more rounds than were recorded: peel eagerly now, and
+    // record twice the rounds on the next call
+    b->kt_rounds *= 2;
+    b->drop_kt_graph();
+  }
   GC_TRY(gc_ktruss(b->g, k, d_mask, cap, stream, nullptr));
   if (b->G == 0) return GC_OK;
   unsigned long long *cnt = static_cast<unsigned long long *>(b->tbuf.ptr);
@@ -421,6 +520,10 @@ extern "C" gc_status gc_batch_ktruss(gc_batch *b, int32_t k, uint8_t *d_mask, in
 extern "C" void gc_batch_free(gc_batch *b) {
   if (!b) return;
   b->drop_graph();
+  b->drop_kt_graph();
+  b->kt.release();
+  dfree(b->kt_mask);
+  dfree(b->kt_cnt);
   if (b->own_stream) (void)hipStreamDestroy(b->own_stream);
   if (b->g) gc_graph_free(b->g);
   dfree(b->vbase);

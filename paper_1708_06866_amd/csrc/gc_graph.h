@@ -179,4 +179,26 @@ gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStre
                              int32_t k_stop = 0x7fffffff, uint8_t *mask = nullptr,
                              int64_t *h_mk = nullptr);
 
+// Device buffers of a k-truss whose launches are recorded once into a HIP
+// graph and replayed (PeelReplay::prepare allocates them before recording).
+struct PeelReplay {
+  DeviceBuffer sup, state, front[2], flag, pos, scan, ctl;
+  int32_t m = 0;
+  gc_status prepare(int32_t m_edges);
+  void release() {
+    dfree(sup); dfree(state); dfree(front[0]); dfree(front[1]);
+    dfree(flag); dfree(pos); dfree(scan); dfree(ctl);
+  }
+  // frontier still pending after the last recorded round of level l + 3
+  // (device, 64 levels at most), 0 where the level ended within its rounds
+  int32_t *leftover() const;
+};
+// The k-truss of g (levels 3 .. k, `rounds` rounds each, no compaction, no
+// frontier sort, no min-support jump) as launches only: no allocation, no
+// host wait, no memset, so the sequence can be recorded into a HIP graph.
+// mask[e] = 1 for the edges of the k-truss when every level ended within
+// its rounds (r.leftover() all 0); otherwise the result is incomplete.
+gc_status ktruss_launches(const gc_graph *g, int32_t k, int32_t rounds, PeelReplay &r,
+                          uint8_t *mask, hipStream_t s);
+
 }  // namespace gc

@@ -878,6 +878,112 @@ static gc_status compact_peel(gc_graph *g, PeelState &ps, CsrView &c, int &next,
   return GC_OK;
 }
 
+// ---- the k-truss as a replayable launch sequence -------------------------
+
+static __global__ void k_fill_u8(uint8_t *__restrict__ x, int64_t n, uint8_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = v;
+}
+
+static __global__ void k_fill_i32n(int32_t *__restrict__ x, int64_t n, int32_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = v;
+}
+
+// A level's first frontier size, read on the device: counter 0 takes it,
+// counters 1 and 2 start at zero.
+static __global__ void k_level_start_dev(int32_t *__restrict__ cnt,
+                                         const int32_t *__restrict__ nfront) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    cnt[0] = *nfront;
+    cnt[1] = 0;
+    cnt[2] = 0;
+  }
+}
+
+static __global__ void k_copy_i32(const int32_t *__restrict__ from, int32_t *__restrict__ to) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *to = *from;
+}
+
+// ctl layout: cnt[16], st[40] (long long), leftover[64]
+struct ReplayCtl {
+  int32_t cnt[16];
+  long long st[40];
+  int32_t leftover[64];
+};
+
+gc_status PeelReplay::prepare(int32_t m_edges) {
+  m = m_edges;
+  const size_t mm = (size_t)m_edges + 1;
+  GC_TRY(dalloc(sup, sizeof(int32_t) * mm));
+  GC_TRY(dalloc(state, mm));
+  GC_TRY(dalloc(front[0], sizeof(int32_t) * mm));
+  GC_TRY(dalloc(front[1], sizeof(int32_t) * mm));
+  GC_TRY(dalloc(flag, sizeof(int32_t) * mm));
+  GC_TRY(dalloc(pos, sizeof(int32_t) * (mm + 64)));
+  const int32_t ntiles = (int32_t)(((int64_t)m_edges + CT_TILE - 1) / CT_TILE);
+  GC_TRY(dalloc(scan, scan_scratch_bytes((int64_t)ntiles + 1)));
+  GC_TRY(dalloc(ctl, sizeof(ReplayCtl)));
+  return GC_OK;
+}
+
+int32_t *PeelReplay::leftover() const { return static_cast<ReplayCtl *>(ctl.ptr)->leftover; }
+
+gc_status ktruss_launches(const gc_graph *g, int32_t k, int32_t rounds, PeelReplay &r,
+                          uint8_t *mask, hipStream_t s) {
+  const int32_t m = (int32_t)g->m;
+  if (m == 0) return GC_OK;
+  if (m != r.m || k - 2 > 64) {
+    set_error("k-truss launches: buffers prepared for another size, or k above 66");
+    return GC_EINVAL;
+  }
+  const CsrView c = g->csr.view(g->n, m);
+  int32_t *sup = static_cast<int32_t *>(r.sup.ptr);
+  uint8_t *state = static_cast<uint8_t *>(r.state.ptr);
+  int32_t *buf[2] = {static_cast<int32_t *>(r.front[0].ptr), static_cast<int32_t *>(r.front[1].ptr)};
+  int32_t *flag = static_cast<int32_t *>(r.flag.ptr), *pos = static_cast<int32_t *>(r.pos.ptr);
+  ReplayCtl *ctl = static_cast<ReplayCtl *>(r.ctl.ptr);
+  k_fill_i32n<<<gsz(sizeof(ReplayCtl) / 4), 256, 0, s>>>(reinterpret_cast<int32_t *>(ctl),
+                                                         (int64_t)(sizeof(ReplayCtl) / 4), 0);
+  k_fill_i32n<<<gsz(m), 256, 0, s>>>(sup, m, 0);
+  k_fill_u8<<<gsz(m), 256, 0, s>>>(state, m, EDGE_ALIVE);
+  GC_LAUNCH_CHECK();
+  GC_TRY(slot_support(c, g->units_sup, sup, s));
+  const int64_t peel_waves = 256 * 64;
+  const unsigned peel_blocks = (unsigned)(peel_waves / (PBLK / 64));
+  const int32_t lb_min = (int32_t)peel_waves;
+  const int32_t ntiles = (int32_t)(((int64_t)m + CT_TILE - 1) / CT_TILE);
+  int32_t *tile_cnt = pos, *tile_pos = pos + ntiles + 1, *tile_live = pos + 3 * (ntiles + 1);
+  for (int32_t kk = 3; kk <= k; ++kk) {
+    const int32_t thr = kk - 2;
+    // first frontier: the live edges with support < thr, in slot order
+    k_collect_tiles<<<ntiles, 256, 0, s>>>(m, thr, state, sup, flag, tile_cnt, nullptr, tile_live);
+    GC_LAUNCH_CHECK();
+    GC_TRY(exclusive_scan(tile_cnt, tile_pos, ntiles, r.scan.ptr, s));
+    k_gather_tiles<<<grid_for(ntiles, 1, 4096), 256, 0, s>>>(flag, tile_cnt, tile_pos, ntiles,
+                                                             buf[0]);
+    k_level_start_dev<<<1, 64, 0, s>>>(ctl->cnt, tile_pos + ntiles);
+    GC_LAUNCH_CHECK();
+    for (int32_t rd = 0; rd < rounds; ++rd) {
+      int32_t *fr = buf[rd & 1], *nx = buf[(rd + 1) & 1];
+      int32_t *cf = &ctl->cnt[rd % 3], *cn = &ctl->cnt[(rd + 1) % 3], *cz = &ctl->cnt[(rd + 2) % 3];
+      k_peel<<<peel_blocks, PBLK, 0, s>>>(c, fr, cf, thr, sup, state, nx, cn, nullptr, lb_min);
+      k_advance<<<1024, 256, 0, s>>>(fr, cf, nx, cn, cz, state, c.eid, nullptr, kk - 1, ctl->st);
+      GC_LAUNCH_CHECK();
+    }
+    // the frontier the next round would take: 0 if the level has ended
+    k_copy_i32<<<1, 64, 0, s>>>(&ctl->cnt[rounds % 3], &ctl->leftover[kk - 3]);
+    GC_LAUNCH_CHECK();
+    // next level: the round buffers start over from buf[0]
+  }
+  k_fill_u8<<<gsz(m), 256, 0, s>>>(mask, m, 0);
+  k_mask_live<<<grid_for(m, 256, 4096), 256, 0, s>>>(state, c.eid, m, mask);
+  GC_LAUNCH_CHECK();
+  return GC_OK;
+}
+
 gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStream_t s,
                              int32_t k_stop, uint8_t *mask, int64_t *h_mk) {
   const int32_t m = (int32_t)g->m;

@@ -124,6 +124,56 @@ def test_graph_replay_with_eager_work_between():
     b.free()
 
 
+def per_graph_check(b, graphs, ref, mask, mk, label):
+    off = b.edge_offsets
+    mask = mask.cpu().numpy()
+    mk = mk.cpu().numpy()
+    for i, (_, _, mr) in enumerate(ref):
+        assert np.array_equal(mask[off[i]:off[i + 1]], mr), (label, i)
+        assert mk[i] == int(mr.sum()), (label, i)
+
+
+def test_ktruss_replay_with_eager_work_between():
+    """The batched k-truss is recorded into a HIP graph on its first call for
+    a k and replayed afterwards: every replay, with eager work on the stream
+    between them, and on a side stream, gives the oracle's k-truss of every
+    graph."""
+    graphs = mixed_graphs(5, count=20)
+    x = torch.arange(1 << 20, device="cuda")
+    for k in (3, 4, 5):
+        ref = oracle_per_graph(graphs, k)
+        say("case batch k-truss replay k=%d" % k)
+        b = gc.build_batch(graphs)
+        for rep in range(4):
+            y = (x * 5 + rep).sum()
+            torch.cuda.synchronize()
+            mask, mk = b.ktruss(k)
+            per_graph_check(b, graphs, ref, mask, mk, (k, rep))
+            assert int(y) >= 0
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            mask, mk = b.ktruss(k, stream=s)
+        s.synchronize()
+        per_graph_check(b, graphs, ref, mask, mk, (k, "side stream"))
+        b.free()
+
+
+def test_ktruss_replay_needs_more_rounds_than_recorded(monkeypatch):
+    """With one round recorded per level (GC_BATCH_KTRUSS_ROUNDS=1), the
+    4-truss levels of R-MAT graphs need more: the call peels eagerly (same
+    result) and the next call records twice the rounds, until a replay
+    converges; every call gives the oracle's k-truss."""
+    monkeypatch.setenv("GC_BATCH_KTRUSS_ROUNDS", "1")
+    graphs = [gg.rmat(12, 16, seed=21), gg.complete(9), gg.king(6)] + mixed_graphs(6, count=8)
+    ref = oracle_per_graph(graphs, 4)
+    say("case batch k-truss re-recorded")
+    b = gc.build_batch(graphs)
+    for rep in range(6):
+        mask, mk = b.ktruss(4)
+        per_graph_check(b, graphs, ref, mask, mk, rep)
+    b.free()
+
+
 def test_batch_edge_cases_and_errors():
     b = gc.build_batch([])
     assert b.n_graphs == 0
