@@ -187,7 +187,8 @@ def algorithmic_bytes(row_ptr: np.ndarray, col: np.ndarray, chunk: int = 128,
     and N+(b) staged once per chunk (4 B each); per in-edge a->b: its packed
     tail range (8 B); per tail element (only x > b can close a triangle): 4 B.
     bytes_by_bin: the same, split by the degree bin of the middle vertex b
-    (d+(b) <= 32, <= 256, <= 2048, <= 8192, larger): one entry per bin."""
+    (d+(b) <= 32, <= 256, <= 2048, <= 8192, larger): one entry per bin.
+    chunk: in-edges per unit, one for all bins or one per bin."""
     n = len(row_ptr) - 1
     m = len(col)
     dout = np.diff(row_ptr).astype(np.int64)
@@ -199,14 +200,16 @@ def algorithmic_bytes(row_ptr: np.ndarray, col: np.ndarray, chunk: int = 128,
     in_edges = int(live.sum())
     din = np.bincount(col, minlength=n).astype(np.int64)
     has = (dout > 0) & (din > 0)
-    chunks = (din[has] + chunk - 1) // chunk
-    units = int(chunks.sum())
-    staged = int((chunks * dout[has]).sum())
-    b = 4 * probes + 8 * in_edges + 4 * staged + 24 * units
     limits = np.asarray(bin_limits, dtype=np.int64)
     nb = len(limits) + 1
     ebin = np.searchsorted(limits, dout[col[live]], side="left")     # bin of each in-edge's b
     vbin = np.searchsorted(limits, dout[has], side="left")           # bin of each middle vertex
+    per_bin = np.broadcast_to(np.asarray(chunk, dtype=np.int64), (nb,))
+    chunk_v = per_bin[vbin]
+    chunks = (din[has] + chunk_v - 1) // chunk_v
+    units = int(chunks.sum())
+    staged = int((chunks * dout[has]).sum())
+    b = 4 * probes + 8 * in_edges + 4 * staged + 24 * units
     probes_b = np.bincount(ebin, weights=tail[live].astype(np.float64), minlength=nb)
     in_b = np.bincount(ebin, minlength=nb)
     units_b = np.bincount(vbin, weights=chunks.astype(np.float64), minlength=nb)
@@ -233,11 +236,12 @@ def count_kernel_name(b: int, strategy: int) -> str:
     return "gc::k_tc_lds<gc::BucketTable<%d> >" % ((4, 7, 10, 12)[b] + (strategy == 4))
 
 
-def profiled_traffic(kernel: str, workload: str, scale: int, ef: int, seed: int, strategy):
+def profiled_traffic(kernel: str, workload: str, scale: int, ef: int, seed: int, strategy,
+                     tile=None):
     """HBM bytes of one launch of `kernel` from the committed rocprofv3
     counter summary (FETCH_SIZE + WRITE_SIZE, each scaled by a plain
     elementwise kernel of known size), if that summary was taken on this
-    workload with these strategies and the count kernels' current source;
+    workload with these strategies and tiles and the count kernels' current source;
     else None (the kernel changed since the counters were taken)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "tc_count_rmat_s24.md")
@@ -255,7 +259,9 @@ def profiled_traffic(kernel: str, workload: str, scale: int, ef: int, seed: int,
     try:
         ok = (kv["count_source_sha256"] == hashlib.sha256(open(src, "rb").read()).hexdigest()
               and kv["workload"] == "%s %d %d %d" % (workload, scale, ef, seed)
-              and [int(x) for x in kv["strategy"].split()] == list(strategy))
+              and [int(x) for x in kv["strategy"].split()] == list(strategy)
+              and [int(x) for x in kv.get("tile", "128 128 128 128 128").split()]
+              == list(tile or [128] * 5))
         return traffic.get(kernel) if ok else None
     except (KeyError, ValueError):
         return None
@@ -677,9 +683,12 @@ def main():
                               os.path.join(tempfile.gettempdir(), "gc_autotune_%d.txt" % os.getpid()))
         g = gc.gc_build_csr(d_src, d_dst, n)
         st, ms = g.autotune()
+        tile = g.count_config()[1]
         g.free()
-        tuned = {"strategy": st.tolist(), "ms": [[round(float(x), 3) for x in row] for row in ms]}
-        log("autotune: strategy per bin %s; ms per bin x strategy %s" % (tuned["strategy"], tuned["ms"]))
+        tuned = {"strategy": st.tolist(), "tile": tile.tolist(),
+                 "ms": [[round(float(x), 3) for x in row] for row in ms]}
+        log("autotune: strategy per bin %s, tile per bin %s; ms per bin x strategy (at the tile) %s"
+            % (tuned["strategy"], tuned["tile"], tuned["ms"]))
 
     def step(record):
         nonlocal tau_buf
@@ -713,7 +722,8 @@ def main():
     # algorithmic bytes of the count pass (host-side, outside the timed region)
     g = gc.gc_build_csr(d_src, d_dst, n)
     _, row_ptr, col, _ = g.oriented()
-    ab = algorithmic_bytes(row_ptr.cpu().numpy(), col.cpu().numpy())
+    ab = algorithmic_bytes(row_ptr.cpu().numpy(), col.cpu().numpy(),
+                           chunk=tuned["tile"] if tuned else 128)
     g.free()
     del row_ptr, col
     torch.cuda.synchronize()
@@ -770,7 +780,8 @@ def main():
     bw = stream_bandwidth(torch, dev)
     log("achievable bandwidth: copy %.0f GB/s (read + write)" % bw["copy_GBps"])
     traffic = None if args.input else profiled_traffic(
-        dom_kernel, args.workload, args.scale, args.ef, args.seed, strategy)
+        dom_kernel, args.workload, args.scale, args.ef, args.seed, strategy,
+        tuned["tile"] if tuned else None)
     out = {
         "metric": "triangle-count and k-truss edges/sec at R-MAT scale 24",
         "value": value,

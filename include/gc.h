@@ -167,13 +167,21 @@ gc_status gc_ktruss(gc_graph *g, int32_t k, uint8_t *d_in_truss, int64_t cap,
  *     only: short lists on both sides)
  * Results never depend on the strategy.  A new handle takes them from the
  * file named by the environment variable GC_AUTOTUNE_CACHE if it exists
- * (lines "<arch> <bin> <strategy>"), else {0, 0, 0, 0, 2}. */
+ * (lines "<arch> <bin> <strategy> <tile>"), else {0, 0, 0, 0, 2}.
+ *
+ * Count tiles per degree bin: the in-edges of a middle vertex b are split
+ * into work units of at most `tile` in-edges (32, 64 or 128), each staging
+ * N+(b) once; smaller units balance the load of vertices with many in-edges
+ * across more workgroups at the cost of staging N+(b) more often.  Results
+ * never depend on the tile.  Default 128 in every bin. */
 
-/* Autotuner: time every admissible strategy of every bin that has work on
- * this graph (HIP events, first run discarded), keep the fastest per bin and,
- * if GC_AUTOTUNE_CACHE is set, write the choices there.  h_strategy[5] and
- * h_ms[5*7] (mean ms per bin and strategy, row-major by bin; -1 where not
- * run) may be NULL.
+/* Autotuner: for each tile (128, 64, 32; the units of every bin rebuilt
+ * with it), time every admissible strategy of every bin that has work on
+ * this graph (HIP events, first run discarded); keep the fastest (strategy,
+ * tile) per bin and, if GC_AUTOTUNE_CACHE is set, write the choices there.
+ * h_strategy[5] and h_ms[5*7] (mean ms per bin and strategy at the tile
+ * chosen for the bin, row-major by bin; -1 where not run) may be NULL; the
+ * chosen tiles are read with gc_graph_count_config.
  * Synchronises `stream`. */
 gc_status gc_graph_autotune(gc_graph *g, gc_stream stream, int32_t *h_strategy,
                             float *h_ms);
@@ -187,6 +195,15 @@ gc_status gc_graph_count_times(const gc_graph *g, float *h_ms, int32_t cap);
 
 /* Set the 5 per-bin strategies (GC_EINVAL if one is not admissible). */
 gc_status gc_graph_set_strategy(gc_graph *g, const int32_t *h_strategy);
+
+/* Set the 5 per-bin count tiles (host array; each 32, 64 or 128, else
+ * GC_EINVAL and nothing changes).  The count units are rebuilt on the next
+ * gc_triangle_count when a tile changes. */
+gc_status gc_graph_set_tile(gc_graph *g, const int32_t *h_tile);
+
+/* The handle's per-bin count strategies and tiles (host arrays of 5; either
+ * may be NULL). */
+gc_status gc_graph_count_config(const gc_graph *g, int32_t *h_strategy, int32_t *h_tile);
 
 /* Truss decomposition (Sec. III-B, last paragraph): d_truss[e] = the largest
  * k such that canonical edge e belongs to the k-truss (>= 2), and *h_kmax the

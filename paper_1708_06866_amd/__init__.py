@@ -88,6 +88,10 @@ def lib():
         L.gc_truss_decomposition.argtypes = [P, P, i64, P, ctypes.POINTER(i32)]
         L.gc_graph_autotune.argtypes = [P, P, P, P]
         L.gc_graph_set_strategy.argtypes = [P, P]
+        L.gc_graph_set_tile.argtypes = [P, P]
+        L.gc_graph_set_tile.restype = i32
+        L.gc_graph_count_config.argtypes = [P, P, P]
+        L.gc_graph_count_config.restype = i32
         L.gc_graph_autotune.restype = i32
         L.gc_graph_set_strategy.restype = i32
         L.gc_graph_truss_stats.argtypes = [P, P, i32]
@@ -297,6 +301,25 @@ class Graph:
         st = np.ascontiguousarray(strategy, dtype=np.int32)
         _check(lib().gc_graph_set_strategy(self.handle, ctypes.c_void_p(st.ctypes.data)),
                "gc_graph_set_strategy")
+
+    def set_tile(self, tile):
+        """Per-bin count tiles (in-edges per work unit: 32, 64 or 128)."""
+        import numpy as np
+        t = np.ascontiguousarray(tile, dtype=np.int32)
+        if t.shape != (N_BINS,):
+            raise ValueError("set_tile: %d tiles needed" % N_BINS)
+        _check(lib().gc_graph_set_tile(self.handle, ctypes.c_void_p(t.ctypes.data)),
+               "gc_graph_set_tile")
+
+    def count_config(self):
+        """(strategy[5], tile[5]) the count uses on this handle."""
+        import numpy as np
+        st = np.zeros(N_BINS, dtype=np.int32)
+        t = np.zeros(N_BINS, dtype=np.int32)
+        _check(lib().gc_graph_count_config(self.handle, ctypes.c_void_p(st.ctypes.data),
+                                           ctypes.c_void_p(t.ctypes.data)),
+               "gc_graph_count_config")
+        return st, t
 
 
 def _handle(g):

@@ -198,7 +198,7 @@ extern "C" gc_status gc_triangle_count(gc_graph *g, gc_stream stream, int64_t *h
     if (g->m == 0) return GC_OK;
     const CsrView c = g->csr.view(g->n, (int32_t)g->m);
     if (!g->units_ready) {
-      GC_TRY(build_units(c, g->units, g->ws, s));
+      GC_TRY(build_units(c, g->units, g->ws, s, g->tile));
       g->units_ready = true;
     }
     GC_TRY(g->ws.reserve(256));
@@ -234,15 +234,38 @@ extern "C" gc_status gc_graph_autotune(gc_graph *g, gc_stream stream, int32_t *h
     float ms[kCountBins * kCountStrategies];
     for (float &x : ms) x = -1.f;
     if (g->m > 0) {
+      // every unit size in turn (the units of all bins rebuilt with it), every
+      // admissible strategy per bin at each; per bin the fastest pair wins
+      // (a later one by 3%, so near-ties keep the larger units)
       const CsrView c = g->csr.view(g->n, (int32_t)g->m);
-      if (!g->units_ready) {
-        GC_TRY(build_units(c, g->units, g->ws, s));
-        g->units_ready = true;
+      constexpr int nt = (int)(sizeof(kTiles) / sizeof(kTiles[0]));
+      float ms_t[nt][kCountBins * kCountStrategies];
+      int st_t[nt][kCountBins];
+      float best[kCountBins];
+      int pick[kCountBins];
+      for (int b = 0; b < kCountBins; ++b) best[b] = -1.f, pick[b] = 0;
+      for (int t = 0; t < nt; ++t) {
+        int ch[kCountBins];
+        for (int b = 0; b < kCountBins; ++b) ch[b] = kTiles[t], st_t[t][b] = g->strategy[b];
+        g->units_ready = false;
+        GC_TRY(build_units(c, g->units, g->ws, s, ch));
+        GC_TRY(g->ws.reserve(256));
+        unsigned long long *d = g->ws.take<unsigned long long>(1);
+        GC_TRY(autotune_bins(c, g->units, st_t[t], ms_t[t], d, nullptr, nullptr, s));
+        for (int b = 0; b < kCountBins; ++b) {
+          const float x = ms_t[t][b * kCountStrategies + st_t[t][b]];
+          if (x >= 0 && (best[b] < 0 || x < 0.97f * best[b])) best[b] = x, pick[b] = t;
+        }
       }
-      GC_TRY(g->ws.reserve(256));
-      unsigned long long *d = g->ws.take<unsigned long long>(1);
-      GC_TRY(autotune_bins(c, g->units, g->strategy, ms, d, nullptr, nullptr, s));
-      save_strategy_cache(g->device, g->strategy);
+      for (int b = 0; b < kCountBins; ++b) {
+        g->strategy[b] = st_t[pick[b]][b];
+        g->tile[b] = kTiles[pick[b]];
+        for (int k = 0; k < kCountStrategies; ++k)
+          ms[b * kCountStrategies + k] = ms_t[pick[b]][b * kCountStrategies + k];
+      }
+      GC_TRY(build_units(c, g->units, g->ws, s, g->tile));
+      g->units_ready = true;
+      save_strategy_cache(g->device, g->strategy, g->tile);
     }
     if (h_strategy)
       for (int b = 0; b < kCountBins; ++b) h_strategy[b] = g->strategy[b];
@@ -285,6 +308,39 @@ extern "C" gc_status gc_graph_set_strategy(gc_graph *g, const int32_t *h_strateg
       return GC_EINVAL;
     }
   for (int b = 0; b < kCountBins; ++b) g->strategy[b] = h_strategy[b];
+  return GC_OK;
+}
+
+extern "C" gc_status gc_graph_set_tile(gc_graph *g, const int32_t *h_tile) {
+  clear_error();
+  if (!g || !h_tile) {
+    set_error("gc_graph_set_tile: invalid argument");
+    return GC_EINVAL;
+  }
+  for (int b = 0; b < kCountBins; ++b)
+    if (!unit_chunk_valid(h_tile[b])) {
+      set_error("gc_graph_set_tile: a unit size is not 32, 64 or 128");
+      return GC_EINVAL;
+    }
+  bool same = true;
+  for (int b = 0; b < kCountBins; ++b) same = same && g->tile[b] == h_tile[b];
+  if (same) return GC_OK;
+  for (int b = 0; b < kCountBins; ++b) g->tile[b] = h_tile[b];
+  g->units_ready = false;  // the next count rebuilds its units
+  return GC_OK;
+}
+
+extern "C" gc_status gc_graph_count_config(const gc_graph *g, int32_t *h_strategy,
+                                           int32_t *h_tile) {
+  clear_error();
+  if (!g) {
+    set_error("gc_graph_count_config: NULL handle");
+    return GC_EINVAL;
+  }
+  for (int b = 0; b < kCountBins; ++b) {
+    if (h_strategy) h_strategy[b] = g->strategy[b];
+    if (h_tile) h_tile[b] = g->tile[b];
+  }
   return GC_OK;
 }
 

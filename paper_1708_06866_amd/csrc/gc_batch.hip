@@ -286,7 +286,7 @@ extern "C" gc_status gc_batch_build(const int32_t *d_src, const int32_t *d_dst,
                      hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return fail(GC_EDEVICE);
-  load_strategy_cache(b->device, b->strategy);
+  load_strategy_cache(b->device, b->strategy, nullptr);
   // rounds recorded per level of the replayed k-truss (GC_BATCH_KTRUSS_ROUNDS)
   if (const char *ev = getenv("GC_BATCH_KTRUSS_ROUNDS")) {
     const long r = strtol(ev, nullptr, 10);
@@ -339,7 +339,7 @@ extern "C" gc_status gc_batch_autotune(gc_batch *b, gc_stream stream, int32_t *h
                          nullptr, static_cast<unsigned long long *>(b->tbuf.ptr),
                          static_cast<const int32_t *>(b->graph_of_rank.ptr), s));
   }
-  save_strategy_cache(b->device, b->strategy);
+  save_strategy_cache(b->device, b->strategy, nullptr);
   if (h_strategy)
     for (int bin = 0; bin < kCountBins; ++bin) h_strategy[bin] = b->strategy[bin];
   if (h_ms)

@@ -331,7 +331,7 @@ extern "C" gc_status gc_build_csr(const int32_t *d_src, const int32_t *d_dst, in
     delete g;
     return GC_EDEVICE;
   }
-  gc::load_strategy_cache(g->device, g->strategy);
+  gc::load_strategy_cache(g->device, g->strategy, g->tile);
   gc_status st = gc::build_impl(d_src, d_dst, n_pairs, n_vertices, flags,
                                 static_cast<hipStream_t>(stream), g);
   // The support kernels' work units belong to the handle from the start, so

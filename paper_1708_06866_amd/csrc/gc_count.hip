@@ -242,18 +242,18 @@ __device__ __forceinline__ int32_t probe_packed(const int32_t *tab, const CsrVie
 // ----------------------------------------------------------------------------
 __global__ void k_unit_counts(const int32_t *__restrict__ row_ptr,
                               const int32_t *__restrict__ in_ptr, int32_t n, int lo, int hi,
-                              int32_t *__restrict__ cnt) {
+                              int32_t chunk, int32_t *__restrict__ cnt) {
   for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n;
        x += (int64_t)gridDim.x * blockDim.x) {
     const int32_t dout = row_ptr[x + 1] - row_ptr[x];
     const int32_t din = in_ptr[x + 1] - in_ptr[x];
-    cnt[x] = (dout > lo && dout <= hi && din > 0) ? (din + UNIT_CHUNK - 1) / UNIT_CHUNK : 0;
+    cnt[x] = (dout > lo && dout <= hi && din > 0) ? (din + chunk - 1) / chunk : 0;
   }
 }
 
 __global__ void k_unit_fill(const int32_t *__restrict__ in_ptr, const int32_t *__restrict__ off,
                             int32_t n, const int32_t *__restrict__ totals, int bin,
-                            int4 *__restrict__ units) {
+                            int32_t chunk, int4 *__restrict__ units) {
   int64_t base = 0;
   for (int b = 0; b < bin; ++b) base += totals[b];
   for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n;
@@ -261,8 +261,8 @@ __global__ void k_unit_fill(const int32_t *__restrict__ in_ptr, const int32_t *_
     const int32_t k0 = off[x], k1 = off[x + 1];
     const int32_t ib = in_ptr[x], ie = in_ptr[x + 1];
     for (int32_t k = k0; k < k1; ++k) {
-      const int32_t b = ib + (k - k0) * UNIT_CHUNK;
-      const int32_t e = b + UNIT_CHUNK < ie ? b + UNIT_CHUNK : ie;
+      const int32_t b = ib + (k - k0) * chunk;
+      const int32_t e = b + chunk < ie ? b + chunk : ie;
       units[base + k] = make_int4((int32_t)x, b, e, bin);
     }
   }
@@ -277,7 +277,13 @@ __global__ void k_copy_total(const int32_t *__restrict__ off, int32_t n, int32_t
 // limits for the split between bins 3 and 4 only when asked; the store keeps
 // one list per limit set.
 static gc_status build_units_with(const CsrView &c, UnitStore &u, Workspace &ws, hipStream_t s,
-                                  bool support_bins) {
+                                  bool support_bins, const int *chunk) {
+  int ch[NBINS];
+  int ch_min = UNIT_CHUNK;
+  for (int b = 0; b < NBINS; ++b) {
+    ch[b] = chunk && unit_chunk_valid(chunk[b]) ? chunk[b] : UNIT_CHUNK;
+    ch_min = ch[b] < ch_min ? ch[b] : ch_min;
+  }
   const int32_t n = c.n;
   GC_TRY(ws.reserve(abytes<int32_t>((size_t)n + 2) * 2 + scan_scratch_bytes(n) +
                     abytes<int32_t>(16)));
@@ -286,18 +292,19 @@ static gc_status build_units_with(const CsrView &c, UnitStore &u, Workspace &ws,
   void *scr = ws.take<char>(scan_scratch_bytes(n));
   int32_t *totals = ws.take<int32_t>(16);
   // upper bound on units: every vertex with in-edges, plus m / chunk
-  const int64_t maxu = (int64_t)n + (int64_t)c.m / UNIT_CHUNK + 1;
+  const int64_t maxu = (int64_t)n + (int64_t)c.m / ch_min + 1;
   GC_TRY(dalloc(u.units, sizeof(int4) * (size_t)maxu));
   const unsigned g = grid_for(n, 256, 65536);
   for (int b = 0; b < NBINS; ++b) {
     const int lo = b == 0 ? 0 : (support_bins ? bin_limit_support(b - 1) : bin_limit_count(b - 1));
     const int hi = support_bins ? bin_limit_support(b) : bin_limit_count(b);
-    k_unit_counts<<<g, 256, 0, s>>>(c.row_ptr, c.in_ptr, n, lo, hi, cnt);
+    k_unit_counts<<<g, 256, 0, s>>>(c.row_ptr, c.in_ptr, n, lo, hi, ch[b], cnt);
     GC_LAUNCH_CHECK();
     GC_TRY(exclusive_scan(cnt, off, n, scr, s));
     k_copy_total<<<1, 64, 0, s>>>(off, n, totals, b);
     GC_LAUNCH_CHECK();
-    k_unit_fill<<<g, 256, 0, s>>>(c.in_ptr, off, n, totals, b, static_cast<int4 *>(u.units.ptr));
+    k_unit_fill<<<g, 256, 0, s>>>(c.in_ptr, off, n, totals, b, ch[b],
+                                  static_cast<int4 *>(u.units.ptr));
     GC_LAUNCH_CHECK();
   }
   int32_t h[NBINS];
@@ -312,13 +319,21 @@ static gc_status build_units_with(const CsrView &c, UnitStore &u, Workspace &ws,
   return GC_OK;
 }
 
-gc_status build_units(const CsrView &c, UnitStore &u, Workspace &ws, hipStream_t s) {
-  return build_units_with(c, u, ws, s, false);
+gc_status build_units(const CsrView &c, UnitStore &u, Workspace &ws, hipStream_t s,
+                      const int *chunk) {
+  GC_TRY(build_units_with(c, u, ws, s, false, chunk));
+  for (int b = 0; b < NBINS; ++b)
+    u.chunk[b] = chunk && unit_chunk_valid(chunk[b]) ? chunk[b] : UNIT_CHUNK;
+  return GC_OK;
 }
 
 gc_status build_units_support(const CsrView &c, UnitStore &u, Workspace &ws, hipStream_t s) {
-  return build_units_with(c, u, ws, s, true);
+  GC_TRY(build_units_with(c, u, ws, s, true, nullptr));
+  for (int b = 0; b < NBINS; ++b) u.chunk[b] = UNIT_CHUNK;
+  return GC_OK;
 }
+
+bool unit_chunk_valid(int chunk) { return chunk == 32 || chunk == 64 || chunk == 128; }
 
 // ----------------------------------------------------------------------------
 // Triangle count
@@ -689,28 +704,34 @@ static std::string arch_of(int dev) {
   return c == std::string::npos ? a : a.substr(0, c);
 }
 
-// Lines "<arch> <bin> <strategy>".
-void load_strategy_cache(int device, int *strategy) {
+// Lines "<arch> <bin> <strategy> [<tile>]" (a line without a tile keeps the
+// tile as it is).
+void load_strategy_cache(int device, int *strategy, int *tile) {
   const char *path = getenv("GC_AUTOTUNE_CACHE");
   if (!path) return;
   FILE *f = fopen(path, "r");
   if (!f) return;
   const std::string arch = arch_of(device);
-  char a[128];
-  int bin, st;
-  while (fscanf(f, "%127s %d %d", a, &bin, &st) == 3)
-    if (arch == a && bin >= 0 && bin < kCountBins && count_strategy_valid(bin, st))
-      strategy[bin] = st;
+  char line[256], a[128];
+  int bin, st, t;
+  while (fgets(line, sizeof line, f)) {
+    const int got = sscanf(line, "%127s %d %d %d", a, &bin, &st, &t);
+    if (got < 3 || arch != a || bin < 0 || bin >= kCountBins || !count_strategy_valid(bin, st))
+      continue;
+    strategy[bin] = st;
+    if (got == 4 && tile && unit_chunk_valid(t)) tile[bin] = t;
+  }
   fclose(f);
 }
 
-void save_strategy_cache(int device, const int *strategy) {
+void save_strategy_cache(int device, const int *strategy, const int *tile) {
   const char *path = getenv("GC_AUTOTUNE_CACHE");
   if (!path) return;
   FILE *f = fopen(path, "w");
   if (!f) return;
   const std::string arch = arch_of(device);
-  for (int bin = 0; bin < kCountBins; ++bin) fprintf(f, "%s %d %d\n", arch.c_str(), bin, strategy[bin]);
+  for (int bin = 0; bin < kCountBins; ++bin)
+    fprintf(f, "%s %d %d %d\n", arch.c_str(), bin, strategy[bin], tile ? tile[bin] : UNIT_CHUNK);
   fclose(f);
 }
 

@@ -56,6 +56,7 @@ struct UnitStore {
   DeviceBuffer units;  // int4 {v, in_begin, in_end, bin}
   int64_t bin_begin[8] = {0};
   int64_t bin_count[8] = {0};
+  int chunk[8] = {128, 128, 128, 128, 128, 128, 128, 128};  // in-edges per unit, per bin
 };
 
 }  // namespace gc
@@ -77,6 +78,7 @@ struct gc_graph {
   gc::UnitStore work_units;
   gc::DeviceBuffer t_sup, t_flag, t_pos, t_misc;  // k-truss round state
   int strategy[5] = {0, 0, 0, 0, 2};             // count strategy per degree bin
+  int tile[5] = {128, 128, 128, 128, 128};       // in-edges per count work unit, per bin
   // last decomposition: [0] levels with removals, [1] rounds, [2] frontier
   // edges, [3] largest frontier, [4] compactions, [5..36] rounds by
   // floor(log2(frontier size)), [37] candidates examined, [38] searched,
@@ -129,7 +131,11 @@ namespace gc {
 gc_status build_in_lists(int32_t n, int32_t m, int bits, CsrStore &c, Workspace &ws,
                          hipStream_t s);
 // (gc_count.hip)
-gc_status build_units(const CsrView &c, UnitStore &u, Workspace &ws, hipStream_t s);
+// Count units with `chunk[b]` in-edges per unit in bin b (32, 64 or 128;
+// null: 128 in every bin).
+gc_status build_units(const CsrView &c, UnitStore &u, Workspace &ws, hipStream_t s,
+                      const int *chunk = nullptr);
+bool unit_chunk_valid(int chunk);
 gc_status build_units_support(const CsrView &c, UnitStore &u, Workspace &ws, hipStream_t s);
 gc_status count_triangles(const CsrView &c, const UnitStore &u, unsigned long long *d_count,
                           hipStream_t s);
@@ -156,9 +162,12 @@ gc_status autotune_bins(const CsrView &c, const UnitStore &u, int *strategy, flo
                         unsigned long long *d_total, unsigned long long *d_per_graph,
                         const int32_t *graph_of_rank, hipStream_t s);
 // Strategy cache file (environment GC_AUTOTUNE_CACHE): load into / save from
-// strategy[kCountBins] for the given device.
-void load_strategy_cache(int device, int *strategy);
-void save_strategy_cache(int device, const int *strategy);
+// strategy[kCountBins] and tile[kCountBins] (either may be null: not loaded,
+// or saved as 128) for the given device.
+void load_strategy_cache(int device, int *strategy, int *tile);
+void save_strategy_cache(int device, const int *strategy, const int *tile);
+// Count-unit sizes the autotuner tries, in order (ties keep the earlier one).
+constexpr int kTiles[3] = {128, 64, 32};
 
 // One graph of a multi-graph count launch (device-side descriptor).
 struct GraphDesc {

@@ -95,6 +95,8 @@ def test_null_handles_rejected_on_the_host(lib):
         ("gc_edge_support_noalloc", [P, P, I64, P], [None, None, 0, None]),
         ("gc_graph_autotune", [P, P, P, P], [None, None, None, None]),
         ("gc_graph_set_strategy", [P, P], [None, None]),
+        ("gc_graph_set_tile", [P, P], [None, None]),
+        ("gc_graph_count_config", [P, P, P], [None, None, None]),
         ("gc_graph_truss_stats", [P, P, I32], [None, None, 0]),
         ("gc_graph_count_times", [P, P, I32], [None, None, 0]),
         ("gc_batch_info", [P, P, P, P], [None, None, None, None]),

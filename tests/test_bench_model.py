@@ -44,12 +44,15 @@ def brute(n, row_ptr, col, chunk, limits):
     probes = sum(1 for a in range(n) for i, b in enumerate(out[a]) if dout[b] > 0
                  for _ in out[a][i + 1:])
     in_edges = sum(1 for a in range(n) for b in out[a] if dout[b] > 0)
-    units = sum(-(-din[b] // chunk) for b in range(n) if dout[b] > 0 and din[b] > 0)
-    staged = sum(-(-din[b] // chunk) * dout[b] for b in range(n) if dout[b] > 0 and din[b] > 0)
     m = len(col)
     # the same bytes by the bin of the middle vertex b (limits inclusive)
     def bin_of(d):
         return sum(1 for lim in limits if d > lim)
+
+    def ch(b):  # the unit size of b's bin
+        return chunk[bin_of(dout[b])] if isinstance(chunk, (list, tuple)) else chunk
+    units = sum(-(-din[b] // ch(b)) for b in range(n) if dout[b] > 0 and din[b] > 0)
+    staged = sum(-(-din[b] // ch(b)) * dout[b] for b in range(n) if dout[b] > 0 and din[b] > 0)
     by_bin = [0] * (len(limits) + 1)
     for a in range(n):
         for i, b in enumerate(out[a]):
@@ -57,7 +60,7 @@ def brute(n, row_ptr, col, chunk, limits):
                 by_bin[bin_of(dout[b])] += 8 + 4 * len(out[a][i + 1:])
     for b in range(n):
         if dout[b] > 0 and din[b] > 0:
-            c = -(-din[b] // chunk)
+            c = -(-din[b] // ch(b))
             by_bin[bin_of(dout[b])] += 24 * c + 4 * c * dout[b]
     return {"S_src": s_src, "S_dst": s_dst, "probes": probes, "in_edges": in_edges,
             "units": units, "staged": staged, "bytes_by_bin": by_bin,
@@ -67,7 +70,9 @@ def brute(n, row_ptr, col, chunk, limits):
 
 def test_algorithmic_bytes_match_brute_force():
     for (src, dst, n), chunk in ((gg.rmat(8, 16, seed=3), 128), (gg.rmat(9, 8, seed=4), 4),
-                                 (gg.complete(40), 8), (gg.king(12), 128), (gg.star(50), 16)):
+                                 (gg.complete(40), 8), (gg.king(12), 128), (gg.star(50), 16),
+                                 (gg.rmat(9, 16, seed=5), [4, 8, 2, 16, 32]),
+                                 (gg.complete(40), [3, 5, 7, 2, 1])):
         u, v = oracle.normalise(src, dst, n)
         row_ptr, col = oriented(n, u, v)
         for limits in (bench.COUNT_BIN_LIMITS, (2, 5, 9, 20)):

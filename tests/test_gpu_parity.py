@@ -449,13 +449,43 @@ def test_count_strategies_agree(strategy):
         g.free()
 
 
+@pytest.mark.parametrize("tile", [[32] * 5, [64] * 5, [32, 64, 128, 32, 64]])
+@pytest.mark.parametrize("strategy", [[0, 0, 0, 0, 2], [3, 5, 2, 4, 2], [6, 6, 3, 3, 2],
+                                      [5, 1, 4, 3, 2]])
+def test_count_tiles_agree(tile, strategy):
+    """Work units of 32 or 64 in-edges give the oracle's count with every
+    strategy (the complete graph puts up to 2299 in-edges on one vertex, so
+    one middle vertex spans up to 72 units)."""
+    for src, dst, n in (gg.rmat(14, 16, seed=2), gg.complete(2300)):
+        g = gc.build_graph(src, dst, n)
+        u, v = oracle.normalise(src, dst, n)
+        want = n * (n - 1) * (n - 2) // 6 if len(u) == n * (n - 1) // 2 else \
+            oracle.triangle_count(n, u, v)
+        g.set_strategy(strategy)
+        assert g.triangle_count() == want
+        g.set_tile(tile)
+        st, t = g.count_config()
+        assert t.tolist() == tile and st.tolist() == strategy
+        assert g.triangle_count() == want, (tile, strategy)
+        g.set_tile([128] * 5)
+        assert g.triangle_count() == want
+        g.free()
+
+
 def test_autotune_keeps_counts():
     src, dst, n = gg.rmat(15, 16, seed=3)
     g = gc.build_graph(src, dst, n)
     T = g.triangle_count()
     st, ms = g.autotune()
-    say("graph autotune", st.tolist(), np.round(ms, 3).tolist())
+    st2, tile = g.count_config()
+    say("graph autotune", st.tolist(), tile.tolist(), np.round(ms, 3).tolist())
     assert st[4] == 2 and g.triangle_count() == T
+    assert st2.tolist() == st.tolist() and set(tile.tolist()) <= {32, 64, 128}
+    with pytest.raises(gc.GCError):
+        g.set_tile([128, 128, 16, 128, 128])
+    with pytest.raises(gc.GCError):
+        g.set_tile([256] * 5)
+    assert g.count_config()[1].tolist() == tile.tolist()
     with pytest.raises(gc.GCError):
         g.set_strategy([0, 0, 0, 0, 1])
     with pytest.raises(gc.GCError):
