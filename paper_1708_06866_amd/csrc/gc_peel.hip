@@ -300,7 +300,11 @@ __device__ __forceinline__ void find_many_lists(const CsrView &c, const bool (&b
 // in lockstep.  When a round starts, the support of a frontier edge equals the
 // number of its triangles still present (every earlier destruction of one of
 // them decremented it while the edge was alive), so an edge with support 0 is
-// skipped and a wave that scans an edge alone stops after that many.
+// skipped and a wave that scans an edge alone stops after that many.  The
+// cases go by falling rank of x and each A is walked from its end (highest
+// rank first): in a degree order the high ranks are the hubs, which close
+// most triangles, so the edge's triangles are met early and the scan stops
+// sooner (R-MAT scale 24: 54.4 G candidates instead of 57.8 G).
 // `work` (optional) holds 4 counters per wave: candidates, searches,
 // triangles found still present, triangles destroyed.
 __global__ __launch_bounds__(PBLK) void k_peel(CsrView c, const int32_t *__restrict__ front,
@@ -338,7 +342,7 @@ __global__ __launch_bounds__(PBLK) void k_peel(CsrView c, const int32_t *__restr
 #pragma unroll
         for (int cs = 0; cs < 3; ++cs) {
           const PeelCase pc = peel_case(pe, p, cs);
-          B.A0[cs][lane] = pc.A0;
+          B.A0[cs][lane] = pc.A0 + pc.nA - 1;  // the last entry: walked downwards
           B.B0[cs][lane] = pc.B0;
           B.B1[cs][lane] = pc.B0 + pc.nB;
           fl |= pc.flags << (2 * cs);
@@ -395,7 +399,7 @@ __global__ __launch_bounds__(PBLK) void k_peel(CsrView c, const int32_t *__restr
               const int cs = local < c0 ? 0 : (local < c1 ? 1 : 2);
               const int32_t li = local - (cs == 0 ? 0 : (cs == 1 ? c0 : c1));
               const uint32_t f2 = B.flags[e] >> (2 * cs);
-              const int32_t i = B.A0[cs][e] + li;
+              const int32_t i = B.A0[cs][e] - li;
               ++n_cand;
               int32_t q, x;
               if (f2 & 1u) {
@@ -473,7 +477,7 @@ __global__ __launch_bounds__(PBLK) void k_peel(CsrView c, const int32_t *__restr
           act[u] = false;
           if (t < nA) {
             ++n_cand;
-            const int32_t i = A0 + t;
+            const int32_t i = A0 + nA - 1 - t;  // highest rank first
             int32_t q, x;
             if (A_in) {
               const int2 ie = c.in_edge[i];
