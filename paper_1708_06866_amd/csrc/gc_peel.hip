@@ -545,11 +545,15 @@ __global__ void k_sum_work(const unsigned long long *__restrict__ w, int64_t nw,
 // clears the counter the round after next appends to (the one this round's
 // predecessor read), and keeps the round statistics: st[0] rounds, st[1]
 // edges removed, st[2] largest round, st[3 + i] rounds with floor(log2 r) = i.
+// With box != null (host-mapped memory) it also leaves the next frontier's
+// size in box[0] and edges removed so far in box[1..2] (low, high 32 bits),
+// so the host reads them after a stream wait, with no copy.
 __global__ void k_advance(const int32_t *__restrict__ front, const int32_t *__restrict__ front_count,
                           const int32_t *__restrict__ next, const int32_t *__restrict__ next_count,
                           int32_t *__restrict__ spare_count, uint8_t *__restrict__ state,
                           const int32_t *__restrict__ eid, int32_t *__restrict__ tau,
-                          int32_t tau_val, long long *__restrict__ st) {
+                          int32_t tau_val, long long *__restrict__ st,
+                          volatile int32_t *__restrict__ box) {
   const int32_t nfront = *front_count, nn = *next_count;
   const int64_t lim = nfront > nn ? nfront : nn;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < lim;
@@ -573,6 +577,12 @@ __global__ void k_advance(const int32_t *__restrict__ front, const int32_t *__re
       st[1] += nfront;
       if (nfront > st[2]) st[2] = nfront;
       st[3 + (31 - __clz(nfront))] += 1;
+    }
+    if (box) {
+      const long long removed = st[1];
+      box[0] = nn;
+      box[1] = (int32_t)(removed & 0xffffffffLL);
+      box[2] = (int32_t)(removed >> 32);
     }
   }
 }
@@ -678,7 +688,8 @@ __global__ __launch_bounds__(256) void k_collect_tiles(int32_t m, int32_t thr,
 __global__ __launch_bounds__(1024) void k_min_live(const int32_t *__restrict__ tile_min,
                                                    const int32_t *__restrict__ tile_live,
                                                    int32_t n, int32_t *__restrict__ dmin,
-                                                   int32_t *__restrict__ dalive) {
+                                                   int32_t *__restrict__ dalive,
+                                                   volatile int32_t *__restrict__ box) {
   __shared__ int32_t smin[16], slive[16];
   int32_t vmin = 0x7fffffff, live = 0;
   for (int32_t i = threadIdx.x; i < n; i += 1024) {
@@ -704,13 +715,19 @@ __global__ __launch_bounds__(1024) void k_min_live(const int32_t *__restrict__ t
     }
     *dmin = vmin;
     *dalive = live;
+    if (box) {  // host-mapped: read after a stream wait
+      box[0] = vmin;
+      box[1] = live;
+    }
   }
 }
 
 // Copy tile b's tile_cnt[b] entries of tmp to front[tile_pos[b] ...).
 __global__ void k_gather_tiles(const int32_t *__restrict__ tmp, const int32_t *__restrict__ tile_cnt,
                                const int32_t *__restrict__ tile_pos, int32_t ntiles,
-                               int32_t *__restrict__ front) {
+                               int32_t *__restrict__ front, volatile int32_t *__restrict__ box) {
+  // the frontier's size, for the host (host-mapped, may be null)
+  if (box && blockIdx.x == 0 && threadIdx.x == 0) *box = tile_pos[ntiles];
   for (int64_t b = blockIdx.x; b < ntiles; b += gridDim.x) {
     const int32_t cnt = tile_cnt[b], at = tile_pos[b];
     const int32_t *src = tmp + b * CT_TILE;
@@ -967,14 +984,15 @@ gc_status ktruss_launches(const gc_graph *g, int32_t k, int32_t rounds, PeelRepl
     GC_LAUNCH_CHECK();
     GC_TRY(exclusive_scan(tile_cnt, tile_pos, ntiles, r.scan.ptr, s));
     k_gather_tiles<<<grid_for(ntiles, 1, 4096), 256, 0, s>>>(flag, tile_cnt, tile_pos, ntiles,
-                                                             buf[0]);
+                                                             buf[0], nullptr);
     k_level_start_dev<<<1, 64, 0, s>>>(ctl->cnt, tile_pos + ntiles);
     GC_LAUNCH_CHECK();
     for (int32_t rd = 0; rd < rounds; ++rd) {
       int32_t *fr = buf[rd & 1], *nx = buf[(rd + 1) & 1];
       int32_t *cf = &ctl->cnt[rd % 3], *cn = &ctl->cnt[(rd + 1) % 3], *cz = &ctl->cnt[(rd + 2) % 3];
       k_peel<<<peel_blocks, PBLK, 0, s>>>(c, fr, cf, thr, sup, state, nx, cn, nullptr, lb_min);
-      k_advance<<<1024, 256, 0, s>>>(fr, cf, nx, cn, cz, state, c.eid, nullptr, kk - 1, ctl->st);
+      k_advance<<<1024, 256, 0, s>>>(fr, cf, nx, cn, cz, state, c.eid, nullptr, kk - 1, ctl->st,
+                                     nullptr);
       GC_LAUNCH_CHECK();
     }
     // the frontier the next round would take: 0 if the level has ended
@@ -1075,14 +1093,26 @@ gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStre
   GC_TRY(dalloc(ps.ctl, sizeof(Ctl)));
   Ctl *ctl = static_cast<Ctl *>(ps.ctl.ptr);
   GC_HIP(hipMemsetAsync(ctl, 0, sizeof(Ctl), s));
-  // host copies of the counters, in pinned memory (fast device-to-host reads)
+  // host copies of the counters, in pinned memory (fast device-to-host
+  // reads), and a mailbox the level-start and retire kernels write directly
+  // (host-mapped, coherent: the stores bypass the GPU caches, so they are
+  // visible once the stream wait returns, with no copy launched)
   struct Pinned {
     void *p = nullptr;
     ~Pinned() { if (p) (void)hipHostFree(p); }
   } pin;
-  GC_HIP(hipHostMalloc(&pin.p, 4096, hipHostMallocDefault));
+  GC_HIP(hipHostMalloc(&pin.p, 4096, hipHostMallocMapped | hipHostMallocCoherent));
   Ctl &h_ctl = *static_cast<Ctl *>(pin.p);
-  int32_t *hq = reinterpret_cast<int32_t *>(static_cast<char *>(pin.p) + 2048);  // min, alive, nf
+  // hq: [0] min support, [1] live edges, [2] first frontier size; hb: [0]
+  // next frontier size, [1..2] edges removed (low, high 32 bits)
+  volatile int32_t *hq = reinterpret_cast<int32_t *>(static_cast<char *>(pin.p) + 2048);
+  volatile int32_t *hb = hq + 16;
+  int32_t *dq = nullptr;  // the mailbox as the device addresses it
+  GC_HIP(hipHostGetDevicePointer(reinterpret_cast<void **>(&dq), const_cast<int32_t *>(hq), 0));
+  int32_t *db = dq + 16;
+  auto removed_so_far = [&]() -> long long {
+    return (long long)(uint32_t)hb[1] | ((long long)hb[2] << 32);
+  };
   long long removed_base = 0;  // edges removed when live was last counted
   int32_t thr_prev = 0;        // threshold of the last level (0 before the first)
 
@@ -1105,23 +1135,21 @@ gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStre
                                              dmin ? tile_min : nullptr, tile_live);
       GC_LAUNCH_CHECK();
       if (dmin) {
-        k_min_live<<<1, 1024, 0, s>>>(tile_min, tile_live, ntiles, dmin, dalive);
+        k_min_live<<<1, 1024, 0, s>>>(tile_min, tile_live, ntiles, dmin, dalive, dq);
         GC_LAUNCH_CHECK();
       }
       GC_TRY(g->ws.reserve(scan_scratch_bytes((int64_t)ntiles + 1)));
       GC_TRY(exclusive_scan(tile_cnt, tile_pos, ntiles,
                             g->ws.take<char>(scan_scratch_bytes((int64_t)ntiles + 1)), s));
       k_gather_tiles<<<grid_for(ntiles, 1, 4096), 256, 0, s>>>(flag, tile_cnt, tile_pos, ntiles,
-                                                               buf[0]);
+                                                               buf[0], dq + 2);
       GC_LAUNCH_CHECK();
-      GC_HIP(hipMemcpyAsync(&hq[2], tile_pos + ntiles, sizeof(int32_t), hipMemcpyDeviceToHost, s));
       return GC_OK;
     };
     const int32_t thr_spec = thr_prev + 1;
     k_set_i32<<<1, 64, 0, s>>>(misc, 0x7fffffff, 0);
     GC_LAUNCH_CHECK();
     GC_TRY(collect(thr_spec, misc, misc + 1));
-    GC_HIP(hipMemcpyAsync(hq, misc, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     GC_HIP(hipStreamSynchronize(s));
     nf = hq[2];
     const int32_t alive = hq[1];
@@ -1175,23 +1203,23 @@ gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStre
         int32_t *cf = &ctl->cnt[r % 3], *cn = &ctl->cnt[(r + 1) % 3], *cz = &ctl->cnt[(r + 2) % 3];
         k_peel<<<peel_blocks, PBLK, 0, s>>>(c, fr, cf, thr, sup, state, nx, cn, work, lb_min);
         GC_LAUNCH_CHECK();
-        k_advance<<<1024, 256, 0, s>>>(fr, cf, nx, cn, cz, state, c.eid, tau, k - 1, ctl->st);
+        k_advance<<<1024, 256, 0, s>>>(fr, cf, nx, cn, cz, state, c.eid, tau, k - 1, ctl->st,
+                                       i + 1 == batch ? db : nullptr);
         GC_LAUNCH_CHECK();
       }
-      GC_HIP(hipMemcpyAsync(&h_ctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
       GC_HIP(hipStreamSynchronize(s));
-      nfront = h_ctl.cnt[r % 3];
+      nfront = hb[0];  // the last retire of the batch left the next size
       if (nfront == 0) break;
-      if ((live - (h_ctl.st[1] - removed_base)) * 4 < (int64_t)c.m * 3) {
+      if ((live - (removed_so_far() - removed_base)) * 4 < (int64_t)c.m * 3) {
         GC_TRY(compact_peel(g, ps, c, next_store, buf[r & 1], nfront, s));
         sup = static_cast<int32_t *>(ps.sup[ps.cur].ptr);
         state = static_cast<uint8_t *>(ps.state[ps.cur].ptr);
         live = c.m;
-        removed_base = h_ctl.st[1];
+        removed_base = removed_so_far();
       }
       batch = batch < 16 ? batch * 2 : 16;
     }
-    removed_base = h_ctl.st[1];
+    removed_base = removed_so_far();
   }
   GC_HIP(hipMemcpyAsync(&h_ctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
   GC_HIP(hipStreamSynchronize(s));
