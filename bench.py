@@ -176,7 +176,7 @@ COUNT_BIN_NAMES = ("d+ <= 32", "d+ 33..256", "d+ 257..2048", "d+ 2049..8192", "d
 
 
 def algorithmic_bytes(row_ptr: np.ndarray, col: np.ndarray, chunk: int = 128,
-                      bin_limits=COUNT_BIN_LIMITS) -> dict:
+                      bin_limits=COUNT_BIN_LIMITS, stage_grid=None) -> dict:
     """Bytes a count pass must move with no cache reuse.
 
     B_model_min: the two whole-list schedules (stage the low vertex and stream
@@ -188,7 +188,12 @@ def algorithmic_bytes(row_ptr: np.ndarray, col: np.ndarray, chunk: int = 128,
     tail range (8 B); per tail element (only x > b can close a triangle): 4 B.
     bytes_by_bin: the same, split by the degree bin of the middle vertex b
     (d+(b) <= 32, <= 256, <= 2048, <= 8192, larger): one entry per bin.
-    chunk: in-edges per unit, one for all bins or one per bin."""
+    chunk: in-edges per unit, one for all bins or one per bin.
+    stage_grid: per bin, None (N+(b) staged once per unit), or the largest
+    grid G of a kernel whose blocks take contiguous stretches of the bin's
+    units (in vertex order): with g = min(G, units of the bin) blocks and
+    ceil(units / g) units per block, N+(b) is staged once per block that holds
+    a unit of b."""
     n = len(row_ptr) - 1
     m = len(col)
     dout = np.diff(row_ptr).astype(np.int64)
@@ -208,12 +213,24 @@ def algorithmic_bytes(row_ptr: np.ndarray, col: np.ndarray, chunk: int = 128,
     chunk_v = per_bin[vbin]
     chunks = (din[has] + chunk_v - 1) // chunk_v
     units = int(chunks.sum())
-    staged = int((chunks * dout[has]).sum())
+    stagings = chunks.copy()                   # times N+(b) is staged, per vertex
+    for bb, grid in enumerate(stage_grid or [None] * nb):
+        sel = np.flatnonzero(vbin == bb)         # the bin's vertices, in rank order
+        if grid is None or len(sel) == 0:
+            continue
+        c_b = chunks[sel]
+        nu = int(c_b.sum())
+        g = min(int(grid), nu)
+        per = -(-nu // g)
+        end = np.cumsum(c_b)
+        first = end - c_b                       # the vertex's units [first, end)
+        stagings[sel] = (end - 1) // per - first // per + 1
+    staged = int((stagings * dout[has]).sum())
     b = 4 * probes + 8 * in_edges + 4 * staged + 24 * units
     probes_b = np.bincount(ebin, weights=tail[live].astype(np.float64), minlength=nb)
     in_b = np.bincount(ebin, minlength=nb)
     units_b = np.bincount(vbin, weights=chunks.astype(np.float64), minlength=nb)
-    staged_b = np.bincount(vbin, weights=(chunks * dout[has]).astype(np.float64), minlength=nb)
+    staged_b = np.bincount(vbin, weights=(stagings * dout[has]).astype(np.float64), minlength=nb)
     by_bin = [int(4 * round(p_) + 8 * int(i_) + 4 * round(s_) + 24 * round(u_))
               for p_, i_, s_, u_ in zip(probes_b, in_b, staged_b, units_b)]
     # the two whole-list schedules of the survey's model, for context
@@ -222,6 +239,22 @@ def algorithmic_bytes(row_ptr: np.ndarray, col: np.ndarray, chunk: int = 128,
     return {"bytes": b, "bytes_by_bin": by_bin, "probes": probes, "in_edges": in_edges,
             "units": units, "staged": staged, "S_src": s_src, "S_dst": s_dst,
             "B_model_min": min(16 * n + 20 * m + 4 * s_dst, 16 * n + 24 * m + 4 * s_src)}
+
+
+def count_stage_grid(b: int, strategy: int):
+    """Largest grid of bin b's count kernel when its blocks take contiguous
+    stretches of units (and stage N+(b) once per stretch), else None: the
+    LDS-table strategies 0, 1, 3, 4 with tables of 16 KB or more (launch
+    configuration of launch_tc_lds in gc_count.hip: 256 CUs x blocks per CU
+    by table size)."""
+    if strategy not in (0, 1, 3, 4) or b >= 4:
+        return None
+    slots = ((1 << (6, 9, 12, 14)[b]) if strategy in (0, 1) else (4 << (4, 7, 10, 12)[b]))
+    tbytes = 4 * slots * (2 if strategy in (1, 4) else 1)
+    if tbytes < 16384:
+        return None
+    per_cu = 512 if tbytes <= 16384 else 64 if tbytes <= 32768 else 32 if tbytes <= 65536 else 16
+    return 256 * per_cu
 
 
 def count_kernel_name(b: int, strategy: int) -> str:
@@ -722,8 +755,10 @@ def main():
     # algorithmic bytes of the count pass (host-side, outside the timed region)
     g = gc.gc_build_csr(d_src, d_dst, n)
     _, row_ptr, col, _ = g.oriented()
+    st_used = tuned["strategy"] if tuned else [0, 0, 0, 0, 2]
     ab = algorithmic_bytes(row_ptr.cpu().numpy(), col.cpu().numpy(),
-                           chunk=tuned["tile"] if tuned else 128)
+                           chunk=tuned["tile"] if tuned else 128,
+                           stage_grid=[count_stage_grid(b, st_used[b]) for b in range(5)])
     g.free()
     del row_ptr, col
     torch.cuda.synchronize()
@@ -763,8 +798,10 @@ def main():
     # The count pass against the HBM roofline.  Its dominant kernel (the
     # launch of the degree bin that takes longest) is measured on its own
     # algorithmic bytes: the schedule's tail model (4 B per tail element
-    # streamed, 8 B per in-edge, 4 B per staged element per unit, 24 B per
-    # unit) over the bin's kernel time from HIP events around that launch on
+    # streamed, 8 B per in-edge, 4 B per staged element each time N+(b) is
+    # staged -- once per unit, or once per block stretch where the kernel's
+    # blocks take contiguous stretches of units -- and 24 B per unit) over
+    # the bin's kernel time from HIP events around that launch on
     # the stream it runs on, averaged over the timed steps.  The whole pass is
     # given beside it, and so is B_TC = min(16n + 20m + 4 S_dst, 16n + 24m +
     # 4 S_src), the whole-list model of Alg. 3 (every element of the streamed
@@ -850,8 +887,9 @@ def main():
             "kernel_ms": float(bin_ms[dom]),
             "algorithmic_bytes": dom_bytes,
             "algorithmic_model": "per launch: 4 B per tail element streamed + 8 B per in-edge "
-                                 "+ 4 B per staged element per unit + 24 B per unit, over the "
-                                 "bin's units",
+                                 "+ 4 B per staged element each time N+(b) is staged (once per "
+                                 "block stretch of the bin's units for the large-table kernels, "
+                                 "else once per unit) + 24 B per unit, over the bin's units",
             "traffic_source": "profiles/tc_count_rmat_s24.md (rocprofv3 FETCH_SIZE + WRITE_SIZE "
                               "per launch, calibrated on an elementwise kernel; null unless "
                               "taken on the current count source with these strategies)",

@@ -356,17 +356,30 @@ __device__ __forceinline__ void stage_row(int32_t *tab, const int32_t *__restric
   __syncthreads();
 }
 
+// contig = 0: block b takes units b, b + grid, ... (interleaved: neighbouring
+// units, which have similar costs, spread over the blocks); contig = 1: block
+// b takes a contiguous stretch of units, and since the units of one middle
+// vertex are consecutive, the block stages N+(b) once for all of its units
+// in the stretch instead of once per unit.
 template <class TB>
 __global__ __launch_bounds__(CBLK) void k_tc_lds(CsrView c, const int4 *__restrict__ units,
-                                                 int64_t nunits, CountOut out) {
+                                                 int64_t nunits, CountOut out, int contig) {
   __shared__ int4 mem[TB::SLOTS / 4];
   __shared__ int32_t poffs[CWAVES][TC_PACK], pxs[CWAVES][TC_PACK];
   int32_t *tab = reinterpret_cast<int32_t *>(mem);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   unsigned long long total = 0;  // wave-uniform
-  for (int64_t ui = blockIdx.x; ui < nunits; ui += gridDim.x) {
+  const int64_t per = contig ? (nunits + gridDim.x - 1) / gridDim.x : 1;
+  const int64_t u0 = contig ? (int64_t)blockIdx.x * per : (int64_t)blockIdx.x;
+  const int64_t u1 = contig ? (u0 + per < nunits ? u0 + per : nunits) : nunits;
+  const int64_t ustep = contig ? 1 : (int64_t)gridDim.x;
+  int32_t staged = -1;  // middle vertex whose N+ the table holds
+  for (int64_t ui = u0; ui < u1; ui += ustep) {
     const int4 U = units[ui];
-    stage_row<TB>(tab, c.col, c.row_ptr[U.x], c.row_ptr[U.x + 1]);
+    if (U.x != staged) {  // block-uniform: every thread reads the same unit
+      stage_row<TB>(tab, c.col, c.row_ptr[U.x], c.row_ptr[U.x + 1]);
+      staged = U.x;
+    }
     const int32_t sum =
         wave_sum_i32(probe_packed<TB>(tab, c, U.y + wave, U.z, lane, poffs[wave], pxs[wave]));
     if (out.per_graph) {
@@ -554,16 +567,28 @@ bool count_strategy_valid(int bin, int strategy) {
   return bin < NBINS - 1 && strategy >= 0 && strategy < kCountStrategies;
 }
 
+// Blocks of the LDS-table count kernel per CU (the grid is at most 256 times
+// this), and whether each block takes a contiguous stretch of units, for a
+// table of `bytes` bytes.  Tables of 16 KB and more (bins 2 and up: long
+// out-lists, and vertices with many units each) stage N+(b) once per stretch;
+// smaller tables interleave their units, whose costs vary more between
+// neighbours (R-MAT scale 24: bin 2 45.0 -> 41.3 ms contiguous, bin 1 4.09 ->
+// 4.53 ms contiguous, so it keeps interleaving).
+constexpr int tc_lds_per_cu(int bytes) {
+  // well above the blocks that fit at once: each block takes a short stretch
+  // of units, and the dispatcher evens out the end (2x: 79.5 ms, 4x: 76.9 ms,
+  // 8x: 73.4 ms, 16x: 72.2 ms for the scale-24 pass; one block per unit:
+  // 123 ms)
+  return bytes <= 8192 ? 256 : bytes <= 16384 ? 512 : bytes <= 32768 ? 64 : bytes <= 65536 ? 32 : 16;
+}
+constexpr bool tc_lds_contig(int bytes) { return bytes >= 16384; }
+
 template <class TB>
 static void launch_tc_lds(const CsrView &c, const int4 *ub, int64_t nu, const CountOut &o,
                           hipStream_t s) {
   constexpr int bytes = TB::SLOTS * 4;
-  // 16 times the blocks that fit at once: each block takes a short stretch of
-  // units, and the dispatcher evens out the end (2x: 79.5 ms, 4x: 76.9 ms,
-  // 8x: 73.4 ms, 16x: 72.2 ms for the scale-24 pass; one block per unit:
-  // 123 ms)
-  constexpr int per_cu = bytes <= 8192 ? 256 : bytes <= 16384 ? 128 : bytes <= 32768 ? 64 : bytes <= 65536 ? 32 : 16;
-  k_tc_lds<TB><<<unit_grid(nu, per_cu), CBLK, 0, s>>>(c, ub, nu, o);
+  k_tc_lds<TB><<<unit_grid(nu, tc_lds_per_cu(bytes)), CBLK, 0, s>>>(c, ub, nu, o,
+                                                                    tc_lds_contig(bytes) ? 1 : 0);
 }
 
 // log2 of linear-probing slots at load <= 1/2 per bin

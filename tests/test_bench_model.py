@@ -30,7 +30,7 @@ def oriented(n, u, v):
     return row_ptr, b.astype(np.int32)
 
 
-def brute(n, row_ptr, col, chunk, limits):
+def brute(n, row_ptr, col, chunk, limits, stage_grid=None):
     out = {a: list(col[row_ptr[a]:row_ptr[a + 1]]) for a in range(n)}
     dout = {a: len(out[a]) for a in range(n)}
     din = {x: 0 for x in range(n)}
@@ -52,7 +52,25 @@ def brute(n, row_ptr, col, chunk, limits):
     def ch(b):  # the unit size of b's bin
         return chunk[bin_of(dout[b])] if isinstance(chunk, (list, tuple)) else chunk
     units = sum(-(-din[b] // ch(b)) for b in range(n) if dout[b] > 0 and din[b] > 0)
-    staged = sum(-(-din[b] // ch(b)) * dout[b] for b in range(n) if dout[b] > 0 and din[b] > 0)
+    # times N+(b) is staged: once per unit, or, where a bin's blocks take
+    # contiguous stretches of its units (listed vertex by vertex in rank
+    # order), once per block holding a unit of b
+    stagings = {b: -(-din[b] // ch(b)) for b in range(n) if dout[b] > 0 and din[b] > 0}
+    for bb, grid in enumerate(stage_grid or []):
+        if grid is None:
+            continue
+        unit_vertex = [b for b in range(n) if b in stagings and bin_of(dout[b]) == bb
+                       for _ in range(-(-din[b] // ch(b)))]
+        if not unit_vertex:
+            continue
+        g = min(grid, len(unit_vertex))
+        per = -(-len(unit_vertex) // g)
+        blocks = {}
+        for i, b in enumerate(unit_vertex):
+            blocks.setdefault(b, set()).add(i // per)
+        for b, bl in blocks.items():
+            stagings[b] = len(bl)
+    staged = sum(stagings[b] * dout[b] for b in stagings)
     by_bin = [0] * (len(limits) + 1)
     for a in range(n):
         for i, b in enumerate(out[a]):
@@ -61,7 +79,7 @@ def brute(n, row_ptr, col, chunk, limits):
     for b in range(n):
         if dout[b] > 0 and din[b] > 0:
             c = -(-din[b] // ch(b))
-            by_bin[bin_of(dout[b])] += 24 * c + 4 * c * dout[b]
+            by_bin[bin_of(dout[b])] += 24 * c + 4 * stagings[b] * dout[b]
     return {"S_src": s_src, "S_dst": s_dst, "probes": probes, "in_edges": in_edges,
             "units": units, "staged": staged, "bytes_by_bin": by_bin,
             "B_model_min": min(16 * n + 20 * m + 4 * s_dst, 16 * n + 24 * m + 4 * s_src),
@@ -76,11 +94,24 @@ def test_algorithmic_bytes_match_brute_force():
         u, v = oracle.normalise(src, dst, n)
         row_ptr, col = oriented(n, u, v)
         for limits in (bench.COUNT_BIN_LIMITS, (2, 5, 9, 20)):
-            got = bench.algorithmic_bytes(row_ptr, col, chunk=chunk, bin_limits=limits)
-            want = brute(n, row_ptr, col, chunk, limits)
-            for k, w in want.items():
-                assert got[k] == w, (k, got[k], w)
-            assert sum(got["bytes_by_bin"]) == got["bytes"]
+            for grid in (None, [None, None, 3, 1, None], [5, 2, 7, 4, 100]):
+                got = bench.algorithmic_bytes(row_ptr, col, chunk=chunk, bin_limits=limits,
+                                              stage_grid=grid)
+                want = brute(n, row_ptr, col, chunk, limits, grid)
+                for k, w in want.items():
+                    assert got[k] == w, (k, grid, got[k], w)
+                assert sum(got["bytes_by_bin"]) == got["bytes"]
+
+
+def test_stage_grid_mirrors_the_launch_configuration():
+    """Bins 2 and 3 with the LDS-table strategies take contiguous stretches
+    (tables of 16 KB and up), bins 0 and 1 and the search and group
+    strategies do not."""
+    assert bench.count_stage_grid(2, 3) == 256 * 512 and bench.count_stage_grid(2, 0) == 256 * 512
+    assert bench.count_stage_grid(2, 4) == 256 * 64 and bench.count_stage_grid(3, 1) == 256 * 16
+    assert bench.count_stage_grid(3, 0) == 256 * 32
+    for b, st in ((0, 0), (1, 3), (1, 4), (2, 2), (0, 5), (1, 6), (4, 2)):
+        assert bench.count_stage_grid(b, st) is None, (b, st)
 
 
 def test_tail_probes_count_the_wedges_once():
