@@ -495,6 +495,38 @@ def test_autotune_keeps_counts():
     g.free()
 
 
+def test_autotune_cache_round_trip(tmp_path, monkeypatch):
+    """The autotuner writes one line per bin (arch, bin, strategy, tile) to
+    GC_AUTOTUNE_CACHE; a new handle takes them; a line without a tile keeps
+    the default tile, and invalid lines are ignored."""
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("GC_AUTOTUNE_CACHE", str(path))
+    src, dst, n = gg.rmat(13, 16, seed=5)
+    u, v = oracle.normalise(src, dst, n)
+    T = oracle.triangle_count(n, u, v)
+    g = gc.build_graph(src, dst, n)
+    st, _ = g.autotune()
+    st_g, tile_g = g.count_config()
+    lines = [ln.split() for ln in path.read_text().splitlines()]
+    assert [int(f[1]) for f in lines] == list(range(5)) and all(len(f) == 4 for f in lines)
+    assert [int(f[2]) for f in lines] == st.tolist() == st_g.tolist()
+    assert [int(f[3]) for f in lines] == tile_g.tolist()
+    h = gc.build_graph(src, dst, n)
+    assert [x.tolist() for x in h.count_config()] == [st_g.tolist(), tile_g.tolist()]
+    arch = lines[0][0]
+    path.write_text("%s 2 3\n%s 1 4 64\n%s 0 6 48\n%s 3 9 32\nother 0 1 32\n"
+                    % (arch, arch, arch, arch))
+    k = gc.build_graph(src, dst, n)
+    st_k, tile_k = k.count_config()
+    assert st_k[2] == 3 and tile_k[2] == 128     # no tile on the line: default kept
+    assert st_k[1] == 4 and tile_k[1] == 64
+    assert st_k[0] == 6 and tile_k[0] == 128     # 48 is not a tile: strategy only
+    assert st_k[3] == 0                          # 9 is not a strategy: line ignored
+    assert k.triangle_count() == T
+    for x in (g, h, k):
+        x.free()
+
+
 @pytest.mark.parametrize("label", ["rmat16", "er16", "K300", "king64"])
 def test_peeling_destroys_each_triangle_once(label):
     """Incremental peeling subtracts every triangle exactly once over the whole
