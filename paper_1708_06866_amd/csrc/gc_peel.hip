@@ -307,16 +307,16 @@ __device__ __forceinline__ void find_many_lists(const CsrView &c, const bool (&b
 // sooner (R-MAT scale 24: 54.4 G candidates instead of 57.8 G).
 // `work` (optional) holds 4 counters per wave: candidates, searches,
 // triangles found still present, triangles destroyed.
-__global__ __launch_bounds__(PBLK) void k_peel(CsrView c, const int32_t *__restrict__ front,
-                                               const int32_t *__restrict__ front_count,
-                                               int32_t thr, int32_t *__restrict__ sup,
-                                               const uint8_t *__restrict__ state,
-                                               int32_t *__restrict__ next,
-                                               int32_t *__restrict__ next_count,
-                                               unsigned long long *__restrict__ work,
-                                               int32_t lb_min) {
+// At most 72 VGPRs, so 7 waves fit per SIMD instead of 6 (a few registers
+// spill to scratch; the extra waves in flight win: R-MAT scale 24
+// decomposition 1300 -> 1289 ms; at 8 waves the spills cost more).
+__global__ __launch_bounds__(PBLK) __attribute__((amdgpu_waves_per_eu(7)))
+void k_peel(CsrView c, const int32_t *__restrict__ front, const int32_t *__restrict__ front_count,
+            int32_t thr, int32_t *__restrict__ sup, const uint8_t *__restrict__ state,
+            int32_t *__restrict__ next, int32_t *__restrict__ next_count,
+            unsigned long long *__restrict__ work, int32_t lb_min) {
   const int lane = threadIdx.x & 63;
-  int32_t n_cand = 0, n_search = 0, n_found = 0, n_ours = 0;  // per-lane work counters
+  int32_t n_cand = 0, n_search = 0, n_found = 0, n_ours = 0;  // this wave's work (uniform)
   const int64_t gw = ((int64_t)blockIdx.x * PBLK + threadIdx.x) >> 6;
   const int64_t nw = ((int64_t)gridDim.x * PBLK) >> 6;
   const int32_t nfront = *front_count;
@@ -379,10 +379,11 @@ __global__ __launch_bounds__(PBLK) void k_peel(CsrView c, const int32_t *__restr
         }
         if (base >= T) break;
         int32_t eu[PEEL_U], qk[PEEL_U], key[PEEL_U], lo[PEEL_U], hi[PEEL_U], hit[PEEL_U];
-        bool bin[PEEL_U], act[PEEL_U];
+        bool bin[PEEL_U], act[PEEL_U], cd[PEEL_U];
 #pragma unroll
         for (int u = 0; u < PEEL_U; ++u) {
           const long long t = base + u * 64 + lane;
+          cd[u] = false;
           eu[u] = 0;
           qk[u] = -1;
           key[u] = 0;
@@ -400,7 +401,7 @@ __global__ __launch_bounds__(PBLK) void k_peel(CsrView c, const int32_t *__restr
               const int32_t li = local - (cs == 0 ? 0 : (cs == 1 ? c0 : c1));
               const uint32_t f2 = B.flags[e] >> (2 * cs);
               const int32_t i = B.A0[cs][e] - li;
-              ++n_cand;
+              cd[u] = true;
               int32_t q, x;
               if (f2 & 1u) {
                 const int2 ie = c.in_edge[i];
@@ -417,10 +418,14 @@ __global__ __launch_bounds__(PBLK) void k_peel(CsrView c, const int32_t *__restr
                 hi[u] = B.B1[cs][e];
                 bin[u] = (f2 & 2u) != 0;
                 act[u] = true;
-                ++n_search;
               }
             }
           }
+        }
+#pragma unroll
+        for (int u = 0; u < PEEL_U; ++u) {
+          n_cand += __popcll(__ballot(cd[u]));
+          n_search += __popcll(__ballot(act[u]));
         }
         find_many_lists(c, bin, lo, hi, key, act, hit);
         bool fnd[PEEL_U];
@@ -434,8 +439,8 @@ __global__ __launch_bounds__(PBLK) void k_peel(CsrView c, const int32_t *__restr
         destroy_many(fnd, pe, qk, hit, thr, state, sup, next, next_count, r);
 #pragma unroll
         for (int u = 0; u < PEEL_U; ++u) {
-          n_found += r[u] & 1;
-          n_ours += r[u] >> 1;
+          n_found += __popcll(__ballot(r[u] & 1));
+          n_ours += __popcll(__ballot(r[u] >> 1));
           if (r[u] & 1) atomicAdd(&B.seen[eu[u]], 1);
         }
         wave_lds_fence();
@@ -468,15 +473,15 @@ __global__ __launch_bounds__(PBLK) void k_peel(CsrView c, const int32_t *__restr
       for (int32_t t0 = sub * 64 + lane; t0 - lane < nA && !(wpe == 1 && seen >= need);
            t0 += stride * PEEL_U) {
         int32_t qk[PEEL_U], key[PEEL_U], hit[PEEL_U];
-        bool act[PEEL_U];
+        bool act[PEEL_U], cd[PEEL_U];
 #pragma unroll
         for (int u = 0; u < PEEL_U; ++u) {
           const int32_t t = t0 + u * stride;
+          cd[u] = t < nA;
           qk[u] = -1;
           key[u] = 0;
           act[u] = false;
           if (t < nA) {
-            ++n_cand;
             const int32_t i = A0 + nA - 1 - t;  // highest rank first
             int32_t q, x;
             if (A_in) {
@@ -491,9 +496,13 @@ __global__ __launch_bounds__(PBLK) void k_peel(CsrView c, const int32_t *__restr
               qk[u] = q;
               key[u] = x;
               act[u] = true;
-              ++n_search;
             }
           }
+        }
+#pragma unroll
+        for (int u = 0; u < PEEL_U; ++u) {
+          n_cand += __popcll(__ballot(cd[u]));
+          n_search += __popcll(__ballot(act[u]));
         }
         if (B_in) find_many(c.in_edge, B0, B1, key, act, hit);
         else find_many(c.col, B0, B1, key, act, hit);
@@ -509,23 +518,20 @@ __global__ __launch_bounds__(PBLK) void k_peel(CsrView c, const int32_t *__restr
         destroy_many(fnd, pe, qk, hit, thr, state, sup, next, next_count, r);
 #pragma unroll
         for (int u = 0; u < PEEL_U; ++u) {
-          n_found += r[u] & 1;
-          n_ours += r[u] >> 1;
-          seen += __popcll(__ballot(r[u] & 1));
+          const int32_t fu = __popcll(__ballot(r[u] & 1));
+          n_found += fu;
+          n_ours += __popcll(__ballot(r[u] >> 1));
+          seen += fu;
         }
       }
     }
   }
   }
-  if (work) {
-    const int32_t a0 = wave_sum_i32(n_cand), a1 = wave_sum_i32(n_search);
-    const int32_t a2 = wave_sum_i32(n_found), a3 = wave_sum_i32(n_ours);
-    if (lane == 0) {  // this wave's own slots: no other wave writes them
-      work[gw * 4 + 0] += (unsigned long long)a0;
-      work[gw * 4 + 1] += (unsigned long long)a1;
-      work[gw * 4 + 2] += (unsigned long long)a2;
-      work[gw * 4 + 3] += (unsigned long long)a3;
-    }
+  if (work && lane == 0) {  // this wave's own slots: no other wave writes them
+    work[gw * 4 + 0] += (unsigned long long)n_cand;
+    work[gw * 4 + 1] += (unsigned long long)n_search;
+    work[gw * 4 + 2] += (unsigned long long)n_found;
+    work[gw * 4 + 3] += (unsigned long long)n_ours;
   }
 }
 
