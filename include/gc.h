@@ -287,9 +287,10 @@ gc_status gc_batch_edge_support(gc_batch *b, int32_t *d_support, int64_t cap,
  * and the per-graph counts) are recorded into a HIP graph on the first call
  * for that k and replayed afterwards; if a level needed more rounds than
  * were recorded, the call peels eagerly instead (same result) and the next
- * call records twice the rounds.  Rounds first recorded per level: 32, or
- * the environment variable GC_BATCH_KTRUSS_ROUNDS read when the batch is
- * built.  cap < Σm gives GC_ECAPACITY.  Synchronises `stream`. */
+ * call records twice the rounds (after a level that 1024 recorded rounds
+ * did not finish, the batch peels eagerly on every call).  Rounds first
+ * recorded per level: 32, or the environment variable GC_BATCH_KTRUSS_ROUNDS
+ * (1 .. 4096) read when the batch is built.  cap < Σm gives GC_ECAPACITY.  Synchronises `stream`. */
 gc_status gc_batch_ktruss(gc_batch *b, int32_t k, uint8_t *d_mask, int64_t cap,
                           int64_t *d_mk, gc_stream stream);
 

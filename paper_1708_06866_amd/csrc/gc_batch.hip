@@ -478,7 +478,7 @@ extern "C" gc_status gc_batch_ktruss(gc_batch *b, int32_t k, uint8_t *d_mask, in
     return GC_ECAPACITY;
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (b->G > 0 && b->g->m > 0 && k > 2 && k - 2 <= 64) {
+  if (b->G > 0 && b->g->m > 0 && k > 2 && k - 2 <= 64 && b->kt_rounds > 0) {
     // the recorded sequence, on the caller's stream (or an own blocking one
     // for the null stream, which cannot be captured)
     hipStream_t cs = s;
@@ -497,8 +497,10 @@ extern "C" gc_status gc_batch_ktruss(gc_batch *b, int32_t k, uint8_t *d_mask, in
       return GC_OK;
     }
     // a level needed more rounds than were recorded: peel eagerly now, and
-    // record twice the rounds on the next call
-    b->kt_rounds *= 2;
+    // record twice the rounds on the next call (up to 1024 rounds per level;
+    // beyond that the sequence would hold too many launches, and this batch
+    // keeps peeling eagerly)
+    b->kt_rounds = b->kt_rounds < 1024 ? b->kt_rounds * 2 : 0;
     b->drop_kt_graph();
   }
   GC_TRY(gc_ktruss(b->g, k, d_mask, cap, stream, nullptr));
