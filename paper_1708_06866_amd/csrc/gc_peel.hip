@@ -39,6 +39,8 @@ enum : uint8_t { EDGE_ALIVE = 0, EDGE_FRONT = 1, EDGE_DEAD = 2 };
 constexpr int PBLK = 256;
 
 constexpr int PEEL_U = 4;  // candidates per lane in flight
+// waves of a peel launch: 56 per CU on the 256 CUs of an MI355X
+constexpr int64_t kPeelWaves = 256 * 56;
 
 // Triangles {p[u], q1[u], q2[u]} seen from frontier edges p[u] (found[u]
 // false: no triangle), the PEEL_U of a lane at once: their state loads, then
@@ -978,7 +980,7 @@ gc_status ktruss_launches(const gc_graph *g, int32_t k, int32_t rounds, PeelRepl
   k_fill_u8<<<gsz(m), 256, 0, s>>>(state, m, EDGE_ALIVE);
   GC_LAUNCH_CHECK();
   GC_TRY(slot_support(c, g->units_sup, sup, s));
-  const int64_t peel_waves = 256 * 64;
+  const int64_t peel_waves = kPeelWaves;
   const unsigned peel_blocks = (unsigned)(peel_waves / (PBLK / 64));
   const int32_t lb_min = (int32_t)peel_waves;
   const int32_t ntiles = (int32_t)(((int64_t)m + CT_TILE - 1) / CT_TILE);
@@ -1054,9 +1056,11 @@ gc_status decomposition_peel(gc_graph *g, int32_t *tau, int32_t *h_kmax, hipStre
                      static_cast<int32_t *>(ps.front[1].ptr)};
   int next_store = 0;
   int32_t kmax = 2;
-  // 64 waves per CU, over twice what is resident: rounds hand out their work
-  // to waves statically, and small shares let the dispatcher even out the end
-  const int64_t peel_waves = 256 * 64;
+  // 56 waves per CU, twice the 28 resident at 7 waves per SIMD: rounds hand
+  // out their work to waves statically, and the second half lets the
+  // dispatcher even out the end (R-MAT scale 24: 1,275 ms, against 1,293 at
+  // 48, 1,288 at 64 and 1,280 at 84 waves per CU)
+  const int64_t peel_waves = kPeelWaves;
   const unsigned peel_blocks = (unsigned)(peel_waves / (PBLK / 64));
   // smallest frontier for the lane-balanced batches (GC_PEEL_LB_MIN; below
   // it, or below one edge per wave, each edge gets whole waves)
