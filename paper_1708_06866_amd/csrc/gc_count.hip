@@ -1045,10 +1045,13 @@ gc_status slot_support(const CsrView &c, const UnitStore &u, int32_t *d_sup, hip
     const int64_t nu = u.bin_count[b];
     if (nu == 0) continue;
     const int4 *ub = units + u.bin_begin[b];
+    // bin 2: many more blocks than fit at once (each takes a few interleaved
+    // units; R-MAT scale 24 support pass 115 -> 110 ms from 64 to 1024 per
+    // CU; one block per unit: 119 ms)
     switch (b) {
       case 0: k_sup_group<6, 16><<<unit_grid((nu + 15) / 16, 16), CBLK, 0, s>>>(c, ub, nu, d_sup); break;
       case 1: k_sup_lds<9><<<unit_grid(nu, 128), CBLK, 0, s>>>(c, ub, nu, d_sup); break;
-      case 2: k_sup_lds<12><<<unit_grid(nu, 64), CBLK, 0, s>>>(c, ub, nu, d_sup); break;
+      case 2: k_sup_lds<12><<<unit_grid(nu, 1024), CBLK, 0, s>>>(c, ub, nu, d_sup); break;
       case 3: k_sup_lds<13><<<unit_grid(nu, 4), CBLK, 0, s>>>(c, ub, nu, d_sup); break;
       default: k_sup_search<<<unit_grid(nu, 8), CBLK, 0, s>>>(c, ub, nu, d_sup); break;
     }
