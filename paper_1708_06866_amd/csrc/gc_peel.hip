@@ -814,24 +814,30 @@ __global__ void k_rows2(const int32_t *__restrict__ row_ptr, const int32_t *__re
 }
 
 // In-list entries whose edge survives a compaction keep their order (each
-// list stays sorted by source): iflag[j] = the edge of in-list entry j lives.
+// list stays sorted by source).  pos is the exclusive scan of the slots'
+// survival flags, so slot s survives iff pos[s + 1] > pos[s], and pos[s] is
+// its new number: one random read of two neighbouring words per entry gives
+// iflag[j] (entry j survives) and nslot[j] (its slot's new number).
 __global__ void k_in_alive(const int2 *__restrict__ in_edge, int32_t m,
-                           const int32_t *__restrict__ flag, int32_t *__restrict__ iflag) {
+                           const int32_t *__restrict__ pos, int32_t *__restrict__ iflag,
+                           int32_t *__restrict__ nslot) {
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m;
-       j += (int64_t)gridDim.x * blockDim.x)
-    iflag[j] = flag[in_edge[j].y];
+       j += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t sl = in_edge[j].y;
+    const int32_t p0 = pos[sl], p1 = pos[sl + 1];
+    iflag[j] = p1 > p0 ? 1 : 0;
+    nslot[j] = p0;
+  }
 }
 
-// Surviving in-list entries to their new places, with their slots renumbered.
+// Surviving in-list entries to their new places, with their slots renumbered
+// (every read coalesced).
 __global__ void k_in_compact(const int2 *__restrict__ in_edge, int32_t m,
                              const int32_t *__restrict__ iflag, const int32_t *__restrict__ ipos,
-                             const int32_t *__restrict__ pos, int2 *__restrict__ nin) {
+                             const int32_t *__restrict__ nslot, int2 *__restrict__ nin) {
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m;
        j += (int64_t)gridDim.x * blockDim.x)
-    if (iflag[j]) {
-      const int2 e = in_edge[j];
-      nin[ipos[j]] = make_int2(e.x, pos[e.y]);
-    }
+    if (iflag[j]) nin[ipos[j]] = make_int2(in_edge[j].x, nslot[j]);
 }
 
 // one element per thread up to 2^28 elements: the compaction kernels do a
@@ -889,14 +895,15 @@ static gc_status compact_peel(gc_graph *g, PeelState &ps, CsrView &c, int &next,
   // carries no in_tail)
   GC_TRY(dalloc(w.in_ptr, sizeof(int32_t) * ((size_t)n + 1)));
   GC_TRY(dalloc(w.in_edge, sizeof(int2) * ((size_t)kept + 1)));
-  const size_t need = 2 * abytes<int32_t>((size_t)m + 1) + scan_scratch_bytes((int64_t)m + 1);
+  const size_t need = 3 * abytes<int32_t>((size_t)m + 1) + scan_scratch_bytes((int64_t)m + 1);
   GC_TRY(g->ws.reserve(need));
   int32_t *iflag = g->ws.take<int32_t>((size_t)m + 1), *ipos = g->ws.take<int32_t>((size_t)m + 1);
+  int32_t *nslot = g->ws.take<int32_t>((size_t)m + 1);
   void *iscr = g->ws.take<char>(scan_scratch_bytes((int64_t)m + 1));
-  k_in_alive<<<gsz(m), 256, 0, s>>>(c.in_edge, m, flag, iflag);
+  k_in_alive<<<gsz(m), 256, 0, s>>>(c.in_edge, m, pos, iflag, nslot);
   GC_LAUNCH_CHECK();
   GC_TRY(exclusive_scan(iflag, ipos, m, iscr, s));
-  k_in_compact<<<gsz(m), 256, 0, s>>>(c.in_edge, m, iflag, ipos, pos,
+  k_in_compact<<<gsz(m), 256, 0, s>>>(c.in_edge, m, iflag, ipos, nslot,
                                       static_cast<int2 *>(w.in_edge.ptr));
   GC_LAUNCH_CHECK();
   k_rows2<<<gsz((int64_t)n + 1), 256, 0, s>>>(c.in_ptr, ipos, n,
