@@ -103,6 +103,33 @@ def test_algorithmic_bytes_match_brute_force():
                 assert sum(got["bytes_by_bin"]) == got["bytes"]
 
 
+def test_stage_grid_matches_the_kernel_source():
+    """count_stage_grid's blocks per CU and stretch rule are the ones the
+    count kernels launch with (read from gc_count.hip)."""
+    import re
+    src = open(os.path.join(ROOT, "paper_1708_06866_amd", "csrc", "gc_count.hip")).read()
+    m = re.search(r"constexpr int tc_lds_per_cu\(int bytes\) \{.*?return (.*?);", src, re.S)
+    assert m, "tc_lds_per_cu not found"
+    steps = [(int(x), int(y)) for x, y in re.findall(r"bytes <= (\d+) \? (\d+)", m.group(1))]
+    last = int(re.search(r": (\d+)\s*$", m.group(1)).group(1))
+
+    def per_cu(nbytes):  # the chain bytes <= x1 ? y1 : bytes <= x2 ? y2 : ... : last
+        for lim, val in steps:
+            if nbytes <= lim:
+                return val
+        return last
+    assert len(steps) >= 3
+    c = re.search(r"constexpr bool tc_lds_contig\(int bytes\) \{ return bytes >= (\d+); \}", src)
+    assert c, "tc_lds_contig not found"
+    contig_min = int(c.group(1))
+    for b in range(4):
+        for st in (0, 1, 3, 4):
+            slots = (1 << (6, 9, 12, 14)[b]) if st in (0, 1) else (4 << (4, 7, 10, 12)[b])
+            tbytes = 4 * slots * (2 if st in (1, 4) else 1)
+            want = 256 * per_cu(tbytes) if tbytes >= contig_min else None
+            assert bench.count_stage_grid(b, st) == want, (b, st, tbytes)
+
+
 def test_stage_grid_mirrors_the_launch_configuration():
     """Bins 2 and 3 with the LDS-table strategies take contiguous stretches
     (tables of 16 KB and up), bins 0 and 1 and the search and group
